@@ -1,0 +1,8 @@
+"""CPU oracle for the closed-shell (T) energy (test infrastructure).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package; the library never does, and the two share no code.
+"""
+from .triples import (triples_energy, triple_restricted, triple_literal, triple_list,
+                      multiplicity, w_tensor, z_tensor, d_tensor, x_piece, problem_energy)
+from .spin_orbital import spin_orbital_triples, connected_antisymmetry_defect

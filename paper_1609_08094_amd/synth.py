@@ -1,0 +1,199 @@
+"""Seeded synthetic inputs for the closed-shell (T) energy.
+
+This module only draws and assembles inputs; it contains none of the (T)
+arithmetic.  It serves both the HIP path and the CPU oracle, which share
+nothing else.
+
+Workload shape (stand-in for the paper's alanine-chain inputs, Sec. 4; the
+paper itself fills its arrays with arbitrary numbers when timing):
+
+* n = o + v spatial orbitals, orbitals 0..o-1 occupied, o..n-1 virtual.
+* Density-fitting factor B[Q, p, q] ~ N(0, 0.1^2), naux = 3 n, made symmetric
+  in (p, q) so that the integrals carry the real-orbital 8-fold symmetry the
+  closed-shell formulas assume (Sec. 2.1, eq. eri_sym_decomp gives the form
+  (pq|rs) = sum_Q B^Q_pq B^Q_rs).
+* eps_occ ~ U[-2.0, -0.3], eps_virt ~ U[0.2, 5.0]; t1 ~ N(0, 1e-3^2).
+* t2 = first-order (MP2) doubles, t^ab_ij = (ia|jb) / (e_i + e_j - e_a - e_b).
+
+Array layouts (C row-major, float64), Mulliken notation:
+  eps_o[o], eps_v[v], t1[i][a], t2[i][j][a][b] = t^ab_ij,
+  vvvo[a][b][c][i] = (ab|ci), ovoo[i][a][j][k] = (ia|jk), ovov[i][a][j][b] = (ia|jb).
+
+Two generators:
+* ``make_problem`` (numpy PCG64, float64 throughout) for every size the host
+  can hold; draw order B, eps_o, eps_v, t1 from ``default_rng(seed)``.
+* ``make_problem_device`` (torch, on the GPU) for the large workloads whose
+  (vv|vo) block does not fit host memory: B is drawn with a seeded torch
+  generator and rounded to bfloat16-representable values, the (vv|vo) product
+  is accumulated in float32 (every product of two bf16 values is exact in
+  float32) and widened to float64; the small blocks are formed in float64.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# sizes of the five workloads: (o, v)
+CONFIGS = {
+    "C0": dict(o=6, v=30),
+    "C1": dict(o=20, v=200),
+    "C2": dict(o=30, v=400),
+    "C3": dict(o=40, v=600),
+}
+BATCH_NPROB = 64
+BATCH_O_RANGE = (4, 16)
+BATCH_V_RANGE = (40, 160)
+
+
+def _symmetrize_B(B: np.ndarray) -> np.ndarray:
+    """Copy the upper triangle (p <= q) of each B^Q onto the lower one."""
+    up = np.triu(B)
+    return up + np.triu(B, 1).transpose(0, 2, 1)
+
+
+def draw_factors(o: int, v: int, seed: int, naux: int | None = None):
+    """Draw (B, eps_o, eps_v, t1) in the fixed order of the recipe."""
+    n = o + v
+    naux = 3 * n if naux is None else naux
+    rng = np.random.default_rng(seed)
+    B = _symmetrize_B(rng.normal(0.0, 0.1, size=(naux, n, n)))
+    eps_o = rng.uniform(-2.0, -0.3, size=o)
+    eps_v = rng.uniform(0.2, 5.0, size=v)
+    t1 = rng.normal(0.0, 1e-3, size=(o, v))
+    return B, eps_o, eps_v, t1
+
+
+def full_eri(B: np.ndarray) -> np.ndarray:
+    """(pq|rs) over all n orbitals, symmetrized to exact 8-fold symmetry.
+
+    Only for tiny n (n^4 doubles)."""
+    g = np.einsum("Qpq,Qrs->pqrs", B, B, optimize=True)
+    g = 0.5 * (g + g.transpose(1, 0, 2, 3))
+    g = 0.5 * (g + g.transpose(0, 1, 3, 2))
+    g = 0.5 * (g + g.transpose(2, 3, 0, 1))
+    return g
+
+
+def _mp2_doubles(ovov: np.ndarray, eps_o: np.ndarray, eps_v: np.ndarray) -> np.ndarray:
+    """t2[i,j,a,b] = (ia|jb) / (e_i + e_j - e_a - e_b)."""
+    den = (eps_o[:, None, None, None] + eps_o[None, :, None, None]
+           - eps_v[None, None, :, None] - eps_v[None, None, None, :])
+    return np.ascontiguousarray(ovov.transpose(0, 2, 1, 3) / den)
+
+
+def make_problem(o: int, v: int, seed: int = 0, naux: int | None = None,
+                 with_eri: bool = False) -> dict:
+    """Host float64 problem.  ``with_eri`` also returns the full 8-fold
+    symmetric ERI tensor ``eri`` (tiny sizes), from which every block is
+    sliced so the blocks agree with it bit for bit."""
+    B, eps_o, eps_v, t1 = draw_factors(o, v, seed, naux)
+    O = slice(0, o)
+    V = slice(o, o + v)
+    out = dict(nocc=o, nvirt=v, eps_o=eps_o, eps_v=eps_v, t1=np.ascontiguousarray(t1))
+    if with_eri:
+        g = full_eri(B)
+        ovov = np.ascontiguousarray(g[O, V, O, V])
+        ovoo = np.ascontiguousarray(g[O, V, O, O])
+        vvvo = np.ascontiguousarray(g[V, V, V, O])
+        out["eri"] = g
+    else:
+        Bov = B[:, O, V]
+        Bvv = B[:, V, V]
+        Boo = B[:, O, O]
+        ovov = np.tensordot(Bov, Bov, axes=([0], [0]))            # [i,a,j,b]
+        ovov = 0.5 * (ovov + ovov.transpose(2, 3, 0, 1))          # (ia|jb) = (jb|ia)
+        ovoo = np.tensordot(Bov, Boo, axes=([0], [0]))            # [i,a,j,k]
+        ovoo = 0.5 * (ovoo + ovoo.transpose(0, 1, 3, 2))          # (ia|jk) = (ia|kj)
+        Bvo = B[:, V, O]
+        vvvo = np.tensordot(Bvv, Bvo, axes=([0], [0]))            # [a,b,c,i]
+        vvvo = 0.5 * (vvvo + vvvo.transpose(1, 0, 2, 3))          # (ab|ci) = (ba|ci)
+        ovov = np.ascontiguousarray(ovov)
+        ovoo = np.ascontiguousarray(ovoo)
+        vvvo = np.ascontiguousarray(vvvo)
+    out["ovov"] = ovov
+    out["ovoo"] = ovoo
+    out["vvvo"] = vvvo
+    out["t2"] = _mp2_doubles(ovov, eps_o, eps_v)
+    return out
+
+
+def batch_shapes(seed: int = 0, nprob: int = BATCH_NPROB):
+    """(o_p, v_p) for the batched workload: o ~ U{4..16}, v ~ U{40..160}."""
+    rng = np.random.default_rng(seed)
+    os_ = rng.integers(BATCH_O_RANGE[0], BATCH_O_RANGE[1] + 1, size=nprob)
+    vs_ = rng.integers(BATCH_V_RANGE[0], BATCH_V_RANGE[1] + 1, size=nprob)
+    return [(int(a), int(b)) for a, b in zip(os_, vs_)]
+
+
+def make_batch(seed: int = 0, nprob: int = BATCH_NPROB) -> list[dict]:
+    """Batched workload: problem p has the drawn shape and uses seed + p."""
+    return [make_problem(o, v, seed + p) for p, (o, v) in enumerate(batch_shapes(seed, nprob))]
+
+
+FIELDS = ("eps_o", "eps_v", "t1", "t2", "vvvo", "ovoo", "ovov")
+
+
+def to_device(prob: dict, device="cuda"):
+    """Copy the float64 arrays of a host problem into torch tensors."""
+    import torch
+    out = dict(nocc=prob["nocc"], nvirt=prob["nvirt"])
+    for f in FIELDS:
+        out[f] = torch.from_numpy(np.ascontiguousarray(prob[f])).to(device)
+    return out
+
+
+def make_problem_device(o: int, v: int, seed: int = 0, naux: int | None = None,
+                        device="cuda", row_chunk: int = 4096) -> dict:
+    """Large-workload generator on the GPU (see module docstring)."""
+    import torch
+    n = o + v
+    naux = 3 * n if naux is None else naux
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    B = torch.randn((naux, n, n), generator=gen, device=device, dtype=torch.float32) * 0.1
+    B = torch.triu(B) + torch.triu(B, 1).transpose(1, 2)
+    B = B.to(torch.bfloat16)                     # bf16-representable factor
+    eps_o = (torch.rand(o, generator=gen, device=device, dtype=torch.float64) * 1.7 - 2.0)
+    eps_v = (torch.rand(v, generator=gen, device=device, dtype=torch.float64) * 4.8 + 0.2)
+    t1 = torch.randn((o, v), generator=gen, device=device, dtype=torch.float64) * 1e-3
+    Bd = B.to(torch.float64)
+    Bov = Bd[:, :o, o:].reshape(naux, o * v)
+    Boo = Bd[:, :o, :o].reshape(naux, o * o)
+    ovov = (Bov.t() @ Bov).reshape(o, v, o, v)
+    ovov = 0.5 * (ovov + ovov.permute(2, 3, 0, 1))
+    ovoo = (Bov.t() @ Boo).reshape(o, v, o, o)
+    ovoo = 0.5 * (ovoo + ovoo.permute(0, 1, 3, 2))
+    den = (eps_o[:, None, None, None] + eps_o[None, :, None, None]
+           - eps_v[None, None, :, None] - eps_v[None, None, None, :])
+    t2 = (ovov.permute(0, 2, 1, 3) / den).contiguous()
+    # (ab|ci): rows (a,b) of Bvv^T times Bvo, accumulated in float32
+    Bvv = B[:, o:, o:].reshape(naux, v * v)
+    Bvo = B[:, o:, :o].reshape(naux, v * o).contiguous()
+    vvvo = torch.empty((v * v, v * o), device=device, dtype=torch.float64)
+    BvvT = Bvv.t()
+    for r0 in range(0, v * v, row_chunk):
+        r1 = min(v * v, r0 + row_chunk)
+        vvvo[r0:r1] = _mm_bf16_f32(BvvT[r0:r1].contiguous(), Bvo).to(torch.float64)
+    vvvo = vvvo.reshape(v, v, v, o)
+    # (ab|ci) = (ba|ci): average each pair of (a-block, b-block) with its
+    # mirror once, so the symmetry is exact whatever the GEMM's sum order.
+    step = 64
+    for a0 in range(0, v, step):
+        a1 = min(v, a0 + step)
+        for b0 in range(a0, v, step):
+            b1 = min(v, b0 + step)
+            s = 0.5 * (vvvo[a0:a1, b0:b1] + vvvo[b0:b1, a0:a1].transpose(0, 1))
+            vvvo[a0:a1, b0:b1] = s
+            vvvo[b0:b1, a0:a1] = s.transpose(0, 1)
+    del B, Bd, Bov, Boo, Bvv, Bvo, BvvT
+    return dict(nocc=o, nvirt=v, eps_o=eps_o.contiguous(), eps_v=eps_v.contiguous(),
+                t1=t1.contiguous(), t2=t2, vvvo=vvvo.contiguous(), ovoo=ovoo.contiguous(),
+                ovov=ovov.contiguous())
+
+
+def _mm_bf16_f32(a, b):
+    """bf16 x bf16 product with float32 accumulation and float32 output."""
+    import torch
+    try:
+        return torch.mm(a, b, out_dtype=torch.float32)
+    except (RuntimeError, TypeError):
+        return torch.mm(a.float(), b.float())
