@@ -1,0 +1,163 @@
+/*
+ * ccsdt.h -- closed-shell CCSD(T) perturbative-triples energy on AMD MI355X
+ * (gfx950), C ABI.
+ *
+ * The operation (Eriksen, arXiv:1609.08094, Sec. 2.2):
+ *
+ *   E(T) = E[4] + E[5]           (eq. piecuch_4th_and_5th_order)
+ *
+ * over canonical Hartree-Fock spatial orbitals, occupied i,j,k,l and virtual
+ * a,b,c,d.  For every occupied triple the library forms the connected
+ * quantity (eq. analytical_triples_ampl, symmetrized by eq. symm_operator)
+ *
+ *   W^abc_ijk = P^abc_ijk [ sum_d (bd|ai) t^cd_kj - sum_l (kc|jl) t^ab_il ]
+ *
+ * the disconnected numerator (eq. piecuch_z_coefficients)
+ *
+ *   Z^abc_ijk = t^a_i (jb|kc) + t^b_j (ia|kc) + t^c_k (ia|jb),   V = W + Z,
+ *
+ * and the denominator-weighted energy with the tilde combination of eq.
+ * piecuch_tilde_quantity, evaluated over restricted triples i<=j<=k (Sec. 3,
+ * task count eq. tasks_ccsdpt) in the equivalent symmetrized form
+ *
+ *   e_ijk = m_ijk/3 sum_abc W_abc [4V_abc + V_bca + V_cab - 2V_acb - 2V_bac - 2V_cba] / D_abc
+ *   D_abc = e_i + e_j + e_k - e_a - e_b - e_c  (< 0),  m = 6 (i<j<k), 3 (two equal),
+ *
+ * E[4] is the same sum with V replaced by W and E[5] with V replaced by Z.
+ * The sign convention of the denominator (negative D, so that E[4] <= 0) is
+ * the reading of the paper this library follows.
+ *
+ * Inputs (all float64, C row-major, real orbitals, Mulliken notation (pq|rs)):
+ *   eps_o[o]            occupied orbital energies
+ *   eps_v[v]            virtual orbital energies
+ *   t1[i][a]            = t^a_i                           (o*v)
+ *   t2[i][j][a][b]      = t^ab_ij                         (o*o*v*v)
+ *   vvvo[a][b][c][i]    = (ab|ci)                         (v*v*v*o)
+ *   ovoo[i][a][j][k]    = (ia|jk)                         (o*v*o*o)
+ *   ovov[i][a][j][b]    = (ia|jb)                         (o*v*o*v)
+ * The elements read are exactly (bd|ai) = vvvo[b][d][a][i],
+ * (kc|jl) = ovoo[k][c][j][l] and (jb|kc) = ovov[j][b][k][c]; no further
+ * symmetry of the inputs is assumed.
+ *
+ * Memory and ownership: every input pointer is a DEVICE pointer (for example
+ * the data pointer of a contiguous torch.float64 tensor on the HIP device).
+ * The caller owns the inputs; the library only reads them, during the call,
+ * and never frees or retains them.  Outputs named *_host are host pointers.
+ * Work runs on the HIP stream passed in (NULL = the default stream); every
+ * call returns after its device work has finished.
+ *
+ * Precision: CCSDT_FP64 runs the contractions on FP64 MFMA; CCSDT_FP32 on
+ * FP32 MFMA with FP32 accumulation (the paper's mixed-precision mode, Sec. 3:
+ * single precision for the triples-amplitude products); CCSDT_BF16X3 splits
+ * each operand x into hi = bf16(x), lo = bf16(x - hi) and accumulates
+ * hi*hi + hi*lo + lo*hi on BF16 MFMA in FP32.  In every mode the
+ * denominators, the t1 terms and all energy sums are FP64 (Sec. 4).
+ *
+ * Errors: every function returns CCSDT_OK (0) or a negative status; on error
+ * outputs are left untouched, nothing is leaked, no exception crosses the
+ * ABI and the process is never aborted.  ccsdt_last_error() returns a
+ * message describing the last non-zero status of the calling thread.
+ */
+#ifndef CCSDT_H
+#define CCSDT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CCSDT_OK = 0,
+    CCSDT_EINVAL = -1,        /* bad argument: null pointer, size < 1, overflow, bad index */
+    CCSDT_ENOMEM = -2,        /* device allocation failed (or exceeded CCSDT_MAX_DEVICE_BYTES) */
+    CCSDT_EHIP = -3,          /* a HIP runtime call failed */
+    CCSDT_EUNSUPPORTED = -4,  /* unknown precision, or no gfx950 device */
+    CCSDT_EDENOM = -5         /* max(eps_o) >= min(eps_v): a denominator is not negative */
+};
+
+typedef enum {
+    CCSDT_FP64 = 0,
+    CCSDT_FP32 = 1,
+    CCSDT_BF16X3 = 2
+} ccsdt_precision;
+
+/* One (T) problem: sizes and device pointers to the seven input blocks,
+ * laid out as described above. */
+typedef struct ccsdt_problem {
+    int nocc;
+    int nvirt;
+    const double* eps_o;
+    const double* eps_v;
+    const double* t1;
+    const double* t2;
+    const double* vvvo;
+    const double* ovoo;
+    const double* ovov;
+} ccsdt_problem;
+
+/* Opaque handle that keeps device workspace (packed operands, the W ring,
+ * partial sums), the tile plan cache and captured graphs between calls.  A
+ * context is bound to the device current at creation and must be used by
+ * one thread at a time. */
+typedef struct ccsdt_context ccsdt_context;
+
+int ccsdt_context_create(ccsdt_context** ctx_out);
+int ccsdt_context_destroy(ccsdt_context* ctx);
+
+/* E(T) of one problem (Sec. 2.2, eqs. piecuch_4th_and_5th_order through
+ * piecuch_tilde_quantity, restricted triples of Sec. 3).
+ * out_host[0] = E(T), out_host[1] = E[4], out_host[2] = E[5]  (Hartree). */
+int ccsdt_energy(ccsdt_context* ctx, const ccsdt_problem* prob, int precision,
+                 void* hip_stream, double* out_host);
+
+/* One-shot convenience form of ccsdt_energy: creates and destroys a
+ * temporary context; *e_out = E(T). */
+int ccsdt_triples_energy(int nocc, int nvirt,
+                         const double* eps_o, const double* eps_v,
+                         const double* t1, const double* t2,
+                         const double* vvvo, const double* ovoo, const double* ovov,
+                         int precision, void* hip_stream, double* e_out);
+
+/* Per-triple energies e_ijk (including the multiplicity m_ijk) of the
+ * restricted triples listed in ijk_host[3*n] (each i<=j<=k< nocc; i=j=k
+ * yields 0).  out_host[3*n] receives (e, e4, e5) per triple. */
+int ccsdt_triple_energies(ccsdt_context* ctx, const ccsdt_problem* prob, int precision,
+                          int ntrip, const int* ijk_host, void* hip_stream,
+                          double* out_host);
+
+/* W^abc_ijk (eq. analytical_triples_ampl bracket, symmetrized by eq.
+ * symm_operator) of one triple i<=j<=k, copied to w_host[a][b][c] (v^3
+ * doubles; widened from FP32 for the mixed precisions).  Test/debug aid. */
+int ccsdt_debug_w(ccsdt_context* ctx, const ccsdt_problem* prob, int precision,
+                  int i, int j, int k, void* hip_stream, double* w_host);
+
+/* Many independent problems of uneven (nocc, nvirt) in one submission: the
+ * triples of all problems form one work list processed by one captured HIP
+ * graph (Sec. 3: loop cycles are data independent).  out_host[3*p+0..2] =
+ * (E, E4, E5) of problem p. */
+int ccsdt_energy_batched(ccsdt_context* ctx, int nprob, const ccsdt_problem* probs_host,
+                         int precision, void* hip_stream, double* out_host);
+
+/* Kernel timing: when enabled, every launch of each kernel class is bracketed
+ * by HIP events on the launch stream, and ccsdt_profile_get returns the
+ * number of launches and their summed duration (ms) since the last reset.
+ * Classes: 0 pack, 1 contract pass A (four permutation terms), 2 contract
+ * pass B (two terms, completes W), 3 energy, 4 reductions. */
+int ccsdt_profile_enable(ccsdt_context* ctx, int on);
+int ccsdt_profile_get(ccsdt_context* ctx, int kernel_class, int64_t* launches,
+                      double* total_ms);
+int ccsdt_profile_reset(ccsdt_context* ctx);
+
+/* Algorithmic flop count (o^3 - o)(2 v^4 + 2 o v^3) of the distinct
+ * contractions under i<=j<=k symmetry, as a double. */
+double ccsdt_flops(int nocc, int nvirt);
+
+/* Message for the calling thread's last non-zero status ("" if none). */
+const char* ccsdt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCSDT_H */

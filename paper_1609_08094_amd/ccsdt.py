@@ -1,0 +1,187 @@
+"""Thin ctypes binding over libccsdt.so (C ABI in include/ccsdt.h).
+
+Argument marshalling only: every step of the (T) computation runs in the
+library's HIP kernels.  Inputs are contiguous float64 torch tensors on the HIP
+device; results come back as Python floats.  If the library is missing the
+binding raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libccsdt.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+STATUS = {0: "CCSDT_OK", -1: "CCSDT_EINVAL", -2: "CCSDT_ENOMEM", -3: "CCSDT_EHIP",
+          -4: "CCSDT_EUNSUPPORTED", -5: "CCSDT_EDENOM"}
+KERNEL_CLASSES = {"pack": 0, "contract_a": 1, "contract_b": 2, "energy": 3, "reduce": 4}
+FIELDS = ("eps_o", "eps_v", "t1", "t2", "vvvo", "ovoo", "ovov")
+EXPORTS = ("ccsdt_context_create", "ccsdt_context_destroy", "ccsdt_energy", "ccsdt_triples_energy",
+           "ccsdt_triple_energies", "ccsdt_debug_w", "ccsdt_energy_batched", "ccsdt_profile_enable",
+           "ccsdt_profile_get", "ccsdt_profile_reset", "ccsdt_flops", "ccsdt_last_error")
+
+
+class CcsdtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("nocc", ctypes.c_int), ("nvirt", ctypes.c_int)] + \
+               [(f, ctypes.c_void_p) for f in FIELDS]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libccsdt.so and declare its signatures (raises if it is absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1609_08094_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+    P = ctypes.POINTER(Problem)
+    lib.ccsdt_context_create.argtypes = [ctypes.POINTER(vp)]
+    lib.ccsdt_context_destroy.argtypes = [vp]
+    lib.ccsdt_energy.argtypes = [vp, P, ip, vp, dp]
+    lib.ccsdt_triples_energy.argtypes = [ip, ip] + [vp] * 7 + [ip, vp, dp]
+    lib.ccsdt_triple_energies.argtypes = [vp, P, ip, ip, ctypes.POINTER(ctypes.c_int), vp, dp]
+    lib.ccsdt_debug_w.argtypes = [vp, P, ip, ip, ip, ip, vp, dp]
+    lib.ccsdt_energy_batched.argtypes = [vp, ip, P, ip, vp, dp]
+    lib.ccsdt_profile_enable.argtypes = [vp, ip]
+    lib.ccsdt_profile_get.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int64), dp]
+    lib.ccsdt_profile_reset.argtypes = [vp]
+    lib.ccsdt_flops.argtypes = [ip, ip]
+    lib.ccsdt_flops.restype = ctypes.c_double
+    lib.ccsdt_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("ccsdt_flops", "ccsdt_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise CcsdtError(rc, load_library().ccsdt_last_error().decode())
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_problem_struct(prob: dict) -> Problem:
+    """Problem struct from a dict of contiguous float64 device tensors."""
+    import torch
+    vals = []
+    for f in FIELDS:
+        t = prob[f]
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous() \
+                or not t.is_cuda:
+            raise ValueError(f"{f} must be a contiguous float64 tensor on the HIP device")
+        vals.append(ctypes.c_void_p(t.data_ptr()))
+    return Problem(int(prob["nocc"]), int(prob["nvirt"]), *vals)
+
+
+def flops(nocc: int, nvirt: int) -> float:
+    return load_library().ccsdt_flops(nocc, nvirt)
+
+
+class Context:
+    """Owns a ccsdt_context (device workspace and plan caches)."""
+
+    def __init__(self):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.ccsdt_context_create(ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ccsdt_context_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- energies -----------------------------------------------------------
+    def energy(self, prob: dict, precision="fp64", stream=None):
+        """(E, E4, E5) of one problem."""
+        p = make_problem_struct(prob)
+        out = (ctypes.c_double * 3)()
+        _check(load_library().ccsdt_energy(self._h, ctypes.byref(p), _prec(precision), _stream(stream), out))
+        return out[0], out[1], out[2]
+
+    def energy_batched(self, probs: list, precision="fp32", stream=None):
+        """[(E, E4, E5)] for many problems in one submission."""
+        arr = (Problem * len(probs))(*[make_problem_struct(p) for p in probs])
+        out = (ctypes.c_double * (3 * len(probs)))()
+        _check(load_library().ccsdt_energy_batched(self._h, len(probs), arr, _prec(precision),
+                                                    _stream(stream), out))
+        return [(out[3 * n], out[3 * n + 1], out[3 * n + 2]) for n in range(len(probs))]
+
+    def triple_energies(self, prob: dict, triples, precision="fp64", stream=None):
+        """[(e, e4, e5)] per restricted triple (i<=j<=k), multiplicity included."""
+        flat = [int(x) for t in triples for x in t]
+        ijk = (ctypes.c_int * len(flat))(*flat)
+        out = (ctypes.c_double * (3 * len(triples)))()
+        p = make_problem_struct(prob)
+        _check(load_library().ccsdt_triple_energies(self._h, ctypes.byref(p), _prec(precision), len(triples),
+                                                     ijk, _stream(stream), out))
+        return [(out[3 * n], out[3 * n + 1], out[3 * n + 2]) for n in range(len(triples))]
+
+    def debug_w(self, prob: dict, i: int, j: int, k: int, precision="fp64", stream=None):
+        """W[a,b,c] of one triple as a float64 numpy array."""
+        import numpy as np
+        v = int(prob["nvirt"])
+        w = np.empty((v, v, v), dtype=np.float64)
+        p = make_problem_struct(prob)
+        _check(load_library().ccsdt_debug_w(self._h, ctypes.byref(p), _prec(precision), i, j, k,
+                                             _stream(stream), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return w
+
+    # -- profiling ----------------------------------------------------------
+    def profile(self, on: bool = True):
+        _check(load_library().ccsdt_profile_enable(self._h, 1 if on else 0))
+
+    def profile_reset(self):
+        _check(load_library().ccsdt_profile_reset(self._h))
+
+    def profile_get(self, cls) -> tuple[int, float]:
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        c = KERNEL_CLASSES[cls] if isinstance(cls, str) else int(cls)
+        _check(load_library().ccsdt_profile_get(self._h, c, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+
+def triples_energy(prob: dict, precision="fp64", stream=None) -> float:
+    """One-shot E(T) through ccsdt_triples_energy."""
+    lib = load_library()
+    vals = make_problem_struct(prob)
+    e = ctypes.c_double()
+    _check(lib.ccsdt_triples_energy(vals.nocc, vals.nvirt, *[getattr(vals, f) for f in FIELDS],
+                                    _prec(precision), _stream(stream), ctypes.byref(e)))
+    return e.value

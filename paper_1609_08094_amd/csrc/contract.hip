@@ -1,0 +1,250 @@
+// Connected triples quantity W (paper Sec. 2.2, eq. analytical_triples_ampl
+// bracket, symmetrized by eq. symm_operator) on gfx950 MFMA.
+//
+// With the packed rows of pack.hip, X^xyz_pqr = <G[p][x][y], T[r][q][z]> and
+//   W^abc_ijk = X^abc_ijk + X^acb_ikj + X^bac_jik + X^bca_jki + X^cab_kij + X^cba_kji.
+// Each term is a batched NT product: one of the two G indices is a batch
+// index, the other the MFMA row, and the T index the MFMA column.  Four terms
+// can be oriented as (row=b, col=c) at fixed a; the two whose T index is a
+// cannot, and are oriented (row=a, col=c) at fixed b:
+//
+//  pass A, batch a, tile (b,c):  W  = <G_i[a][b],T_kj[c]> + <T_jk[b],G_i[a][c]>
+//                                   + <G_j[b][a],T_ki[c]> + <T_ji[b],G_k[c][a]>
+//  pass B, batch b, tile (a,c):  W += <T_ik[a],G_j[b][c]> + <T_ij[a],G_k[c][b]>
+//
+// so every W element is written once by pass A and updated once by pass B;
+// the four (two) terms of a pass run as one K loop over 4 (2) segments of
+// length Kp.  Output is W[a][b][c] (FP64 for the FP64 path, FP32 otherwise).
+//
+// MFMA shapes (all with a 16x16 output block; lane l holds four rows of
+// column l%16: rows l/16 + 4r for the FP64 instruction, 4(l/16) + r for the
+// FP32-accumulating ones, r < 4):
+//   FP64    v_mfma_f64_16x16x4_f64     4 steps per 16-element chunk
+//   FP32    v_mfma_f32_16x16x4_f32     4 steps per 16-element chunk
+//   BF16X3  v_mfma_f32_16x16x32_bf16   hi*hi + hi*lo + lo*hi per 32-element chunk
+// Within a chunk each lane owns a contiguous run of k; A and B use the same
+// assignment, so the dot product covers every k exactly once.
+#include "common.hpp"
+
+namespace ccsdt {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Workgroups are dispatched round-robin over the XCDs; give each XCD a
+// contiguous range of logical work so tiles sharing operand rows share an L2.
+__device__ __forceinline__ int xcd_remap(int bid, int total) {
+    const int q = total / NXCD, r = total % NXCD;
+    const int x = bid % NXCD, idx = bid / NXCD;
+    return x * q + min(x, r) + idx;
+}
+
+struct PrecF64 {
+    using E = double;
+    using W = double;
+    using Acc = f64x4;
+    static constexpr int KCH = 16;
+    static constexpr int UNITS = 1;
+    struct Frag { f64x4 x; };
+    static __device__ __forceinline__ int out_row(int lane, int r) { return (lane >> 4) + 4 * r; }
+    static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
+        f.x = *reinterpret_cast<const f64x4*>(row + c * 16 + 4 * (lane >> 4));
+    }
+    static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[0], b.x[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[1], b.x[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[2], b.x[2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[3], b.x[3], acc, 0, 0, 0);
+    }
+};
+
+struct PrecF32 {
+    using E = float;
+    using W = float;
+    using Acc = f32x4;
+    static constexpr int KCH = 16;
+    static constexpr int UNITS = 1;
+    struct Frag { f32x4 x; };
+    static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+    static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
+        f.x = *reinterpret_cast<const f32x4*>(row + c * 16 + 4 * (lane >> 4));
+    }
+    static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[0], b.x[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[1], b.x[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[2], b.x[2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[3], b.x[3], acc, 0, 0, 0);
+    }
+};
+
+struct PrecB3 {
+    using E = uint16_t;
+    using W = float;
+    using Acc = f32x4;
+    static constexpr int KCH = 32;
+    static constexpr int UNITS = 2;
+    struct Frag { bf16x8 hi, lo; };
+    static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+    static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
+        const E* p = row + (c * 4 + (lane >> 4)) * 16;
+        f.hi = *reinterpret_cast<const bf16x8*>(p);
+        f.lo = *reinterpret_cast<const bf16x8*>(p + 8);
+    }
+    static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc, 0, 0, 0);
+    }
+};
+
+// Row indices (in packed rows) of the operands of one segment.
+struct SegRows {
+    int64_t a0, aB, aM;  // A row = a0 + beta*aB + m*aM   (from G if aG else T)
+    int64_t b0, bB, bN;  // B row = b0 + beta*bB + n*bN
+    bool aG, bG;
+};
+
+__device__ __forceinline__ SegRows segment(int pass, int s, int i, int j, int k, int o, int v) {
+    const int64_t V = v, V2 = (int64_t)v * v;
+    auto trow = [&](int r, int q) { return ((int64_t)r * o + q) * V; };  // first row of T[r][q]
+    SegRows g{};
+    if (pass == 0) {  // batch a, row b, col c
+        switch (s) {
+            case 0: g = {i * V2, V, 1, trow(k, j), 0, 1, true, false}; break;   // G_i[a][b] . T_kj[c]
+            case 1: g = {trow(j, k), 0, 1, i * V2, V, 1, false, true}; break;   // T_jk[b] . G_i[a][c]
+            case 2: g = {j * V2, 1, V, trow(k, i), 0, 1, true, false}; break;   // G_j[b][a] . T_ki[c]
+            default: g = {trow(j, i), 0, 1, k * V2, 1, V, false, true}; break;  // T_ji[b] . G_k[c][a]
+        }
+    } else {  // batch b, row a, col c
+        switch (s) {
+            case 0: g = {trow(i, k), 0, 1, j * V2, V, 1, false, true}; break;   // T_ik[a] . G_j[b][c]
+            default: g = {trow(i, j), 0, 1, k * V2, 1, V, false, true}; break;  // T_ij[a] . G_k[c][b]
+        }
+    }
+    return g;
+}
+
+template <class P, int WM, int WN>
+__global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ slots, int nslot, int pass,
+                                                       int total) {
+    using E = typename P::E;
+    using Wt = typename P::W;
+    const int bid = xcd_remap(blockIdx.x, total);
+    int lo = 0, hi = nslot - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int b = pass ? slots[mid].b_begin : slots[mid].a_begin;
+        if (b <= bid) lo = mid; else hi = mid - 1;
+    }
+    const Slot* S = slots + lo;
+    const int v = S->v, o = S->o, Kp = S->Kp;
+    const int tn = S->tiles_n;
+    int local = bid - (pass ? S->b_begin : S->a_begin);
+    const int per_beta = S->tiles_m * tn;
+    const int beta = local / per_beta;
+    local -= beta * per_beta;
+    const int tmi = local / tn, tni = local - (local / tn) * tn;
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m0 = tmi * (32 * WM) + (wave >> 1) * (16 * WM);
+    const int n0 = tni * (32 * WN) + (wave & 1) * (16 * WN);
+    const int vm = min(WM, (v - m0 + 15) / 16);  // valid 16-row blocks of this wave
+    const int vn = min(WN, (v - n0 + 15) / 16);
+    if (m0 >= v || n0 >= v) return;  // no barrier in this kernel: idle waves may leave
+
+    typename P::Acc acc[WM][WN];
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b) acc[a][b] = typename P::Acc{};
+
+    const int64_t rl = (int64_t)Kp * P::UNITS;
+    const E* G = static_cast<const E*>(S->gc);
+    const E* T = static_cast<const E*>(S->tc);
+    const int nseg = pass ? 2 : 4;
+    const int nch = Kp / P::KCH;
+    for (int s = 0; s < nseg; ++s) {
+        const SegRows g = segment(pass, s, S->i, S->j, S->k, o, v);
+        const E* pa[WM];
+        const E* pb[WN];
+#pragma unroll
+        for (int a = 0; a < WM; ++a) {
+            const int m = min(m0 + a * 16 + (lane & 15), v - 1);
+            pa[a] = (g.aG ? G : T) + (g.a0 + beta * g.aB + m * g.aM) * rl;
+        }
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+            const int n = min(n0 + b * 16 + (lane & 15), v - 1);
+            pb[b] = (g.bG ? G : T) + (g.b0 + beta * g.bB + n * g.bN) * rl;
+        }
+        typename P::Frag fa[WM], fb[WN];
+#pragma unroll
+        for (int a = 0; a < WM; ++a) if (a < vm) P::load(fa[a], pa[a], 0, lane);
+#pragma unroll
+        for (int b = 0; b < WN; ++b) if (b < vn) P::load(fb[b], pb[b], 0, lane);
+        for (int c = 0; c < nch; ++c) {
+            typename P::Frag na[WM], nb[WN];
+            if (c + 1 < nch) {
+#pragma unroll
+                for (int a = 0; a < WM; ++a) if (a < vm) P::load(na[a], pa[a], c + 1, lane);
+#pragma unroll
+                for (int b = 0; b < WN; ++b) if (b < vn) P::load(nb[b], pb[b], c + 1, lane);
+            }
+#pragma unroll
+            for (int a = 0; a < WM; ++a)
+#pragma unroll
+                for (int b = 0; b < WN; ++b)
+                    if (a < vm && b < vn) P::mma(acc[a][b], fa[a], fb[b]);
+#pragma unroll
+            for (int a = 0; a < WM; ++a) fa[a] = na[a];
+#pragma unroll
+            for (int b = 0; b < WN; ++b) fb[b] = nb[b];
+        }
+    }
+
+    Wt* out = static_cast<Wt*>(S->w);
+    const int64_t V = v, V2 = (int64_t)v * v;
+    const int64_t oB = pass ? V : V2, oM = pass ? V2 : V;
+#pragma unroll
+    for (int a = 0; a < WM; ++a) {
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+            if (a < vm && b < vn) {
+                const int n = n0 + b * 16 + (lane & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = m0 + a * 16 + P::out_row(lane, r);
+                    if (m < v && n < v) {
+                        const int64_t idx = beta * oB + m * oM + n;
+                        const Wt val = (Wt)acc[a][b][r];
+                        if (pass) out[idx] += val; else out[idx] = val;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <class P>
+static hipError_t contract_impl(int cfg, int pass, const Slot* d_slots, int nslot, int total, hipStream_t s) {
+    switch (cfg) {
+        case 0: hipLaunchKernelGGL((contract_kernel<P, 2, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
+        case 1: hipLaunchKernelGGL((contract_kernel<P, 4, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
+        case 2: hipLaunchKernelGGL((contract_kernel<P, 4, 4>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_contract(int prec, int cfg, int pass, const Slot* d_slots, int nslot, int total, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    switch (prec) {
+        case P_FP64: return contract_impl<PrecF64>(cfg, pass, d_slots, nslot, total, s);
+        case P_FP32: return contract_impl<PrecF32>(cfg, pass, d_slots, nslot, total, s);
+        case P_BF16X3: return contract_impl<PrecB3>(cfg, pass, d_slots, nslot, total, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ccsdt

@@ -22,11 +22,9 @@ Array layouts (C row-major, float64), Mulliken notation:
 Two generators:
 * ``make_problem`` (numpy PCG64, float64 throughout) for every size the host
   can hold; draw order B, eps_o, eps_v, t1 from ``default_rng(seed)``.
-* ``make_problem_device`` (torch, on the GPU) for the large workloads whose
-  (vv|vo) block does not fit host memory: B is drawn with a seeded torch
-  generator and rounded to bfloat16-representable values, the (vv|vo) product
-  is accumulated in float32 (every product of two bf16 values is exact in
-  float32) and widened to float64; the small blocks are formed in float64.
+* ``make_problem_device`` for the large workloads whose (vv|vo) block does
+  not fit host memory: the same draws on the host, the same float64 products
+  formed on the GPU with torch (summation order may differ in the last bit).
 """
 from __future__ import annotations
 
@@ -142,58 +140,48 @@ def to_device(prob: dict, device="cuda"):
 
 
 def make_problem_device(o: int, v: int, seed: int = 0, naux: int | None = None,
-                        device="cuda", row_chunk: int = 4096) -> dict:
-    """Large-workload generator on the GPU (see module docstring)."""
+                        device="cuda", row_chunk: int = 8192) -> dict:
+    """Same recipe and the same random draws as ``make_problem`` (numpy
+    PCG64 on the host), with the integral products formed in float64 on the
+    GPU, for workloads whose (vv|vo) block does not fit host memory."""
     import torch
-    n = o + v
-    naux = 3 * n if naux is None else naux
-    gen = torch.Generator(device=device)
-    gen.manual_seed(int(seed))
-    B = torch.randn((naux, n, n), generator=gen, device=device, dtype=torch.float32) * 0.1
-    B = torch.triu(B) + torch.triu(B, 1).transpose(1, 2)
-    B = B.to(torch.bfloat16)                     # bf16-representable factor
-    eps_o = (torch.rand(o, generator=gen, device=device, dtype=torch.float64) * 1.7 - 2.0)
-    eps_v = (torch.rand(v, generator=gen, device=device, dtype=torch.float64) * 4.8 + 0.2)
-    t1 = torch.randn((o, v), generator=gen, device=device, dtype=torch.float64) * 1e-3
-    Bd = B.to(torch.float64)
+    B, eps_o, eps_v, t1 = draw_factors(o, v, seed, naux)
+    naux = B.shape[0]
+    Bd = torch.from_numpy(B).to(device)
+    del B
+    eps_o = torch.from_numpy(eps_o).to(device)
+    eps_v = torch.from_numpy(eps_v).to(device)
+    t1 = torch.from_numpy(np.ascontiguousarray(t1)).to(device)
     Bov = Bd[:, :o, o:].reshape(naux, o * v)
     Boo = Bd[:, :o, :o].reshape(naux, o * o)
     ovov = (Bov.t() @ Bov).reshape(o, v, o, v)
-    ovov = 0.5 * (ovov + ovov.permute(2, 3, 0, 1))
+    ovov = (0.5 * (ovov + ovov.permute(2, 3, 0, 1))).contiguous()     # (ia|jb) = (jb|ia)
     ovoo = (Bov.t() @ Boo).reshape(o, v, o, o)
-    ovoo = 0.5 * (ovoo + ovoo.permute(0, 1, 3, 2))
+    ovoo = (0.5 * (ovoo + ovoo.permute(0, 1, 3, 2))).contiguous()     # (ia|jk) = (ia|kj)
     den = (eps_o[:, None, None, None] + eps_o[None, :, None, None]
            - eps_v[None, None, :, None] - eps_v[None, None, None, :])
     t2 = (ovov.permute(0, 2, 1, 3) / den).contiguous()
-    # (ab|ci): rows (a,b) of Bvv^T times Bvo, accumulated in float32
-    Bvv = B[:, o:, o:].reshape(naux, v * v)
-    Bvo = B[:, o:, :o].reshape(naux, v * o).contiguous()
+    Bvv = Bd[:, o:, o:].reshape(naux, v * v)
+    Bvo = Bd[:, o:, :o].reshape(naux, v * o).contiguous()
+    del Bd
     vvvo = torch.empty((v * v, v * o), device=device, dtype=torch.float64)
     BvvT = Bvv.t()
     for r0 in range(0, v * v, row_chunk):
         r1 = min(v * v, r0 + row_chunk)
-        vvvo[r0:r1] = _mm_bf16_f32(BvvT[r0:r1].contiguous(), Bvo).to(torch.float64)
+        torch.matmul(BvvT[r0:r1], Bvo, out=vvvo[r0:r1])
+    del Bvv, BvvT, Bvo
     vvvo = vvvo.reshape(v, v, v, o)
-    # (ab|ci) = (ba|ci): average each pair of (a-block, b-block) with its
-    # mirror once, so the symmetry is exact whatever the GEMM's sum order.
+    # (ab|ci) = (ba|ci): average each (a-block, b-block) pair with its mirror
+    # once, so the symmetry is exact whatever the GEMM's summation order.
     step = 64
     for a0 in range(0, v, step):
         a1 = min(v, a0 + step)
         for b0 in range(a0, v, step):
             b1 = min(v, b0 + step)
-            s = 0.5 * (vvvo[a0:a1, b0:b1] + vvvo[b0:b1, a0:a1].transpose(0, 1))
-            vvvo[a0:a1, b0:b1] = s
-            vvvo[b0:b1, a0:a1] = s.transpose(0, 1)
-    del B, Bd, Bov, Boo, Bvv, Bvo, BvvT
-    return dict(nocc=o, nvirt=v, eps_o=eps_o.contiguous(), eps_v=eps_v.contiguous(),
-                t1=t1.contiguous(), t2=t2, vvvo=vvvo.contiguous(), ovoo=ovoo.contiguous(),
-                ovov=ovov.contiguous())
+            sym = 0.5 * (vvvo[a0:a1, b0:b1] + vvvo[b0:b1, a0:a1].transpose(0, 1))
+            vvvo[a0:a1, b0:b1] = sym
+            vvvo[b0:b1, a0:a1] = sym.transpose(0, 1)
+    return dict(nocc=o, nvirt=v, eps_o=eps_o, eps_v=eps_v, t1=t1, t2=t2, vvvo=vvvo,
+                ovoo=ovoo, ovov=ovov)
 
 
-def _mm_bf16_f32(a, b):
-    """bf16 x bf16 product with float32 accumulation and float32 output."""
-    import torch
-    try:
-        return torch.mm(a, b, out_dtype=torch.float32)
-    except (RuntimeError, TypeError):
-        return torch.mm(a.float(), b.float())

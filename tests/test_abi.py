@@ -1,0 +1,59 @@
+"""C-ABI library: loads, exports every declared symbol, host-only entry points.
+
+No GPU compute is issued here: only calls that return before touching a
+device (argument errors, the flop formula, the error string).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1609_08094_amd import ccsdt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ccsdt.h")
+
+
+def _lib():
+    if not os.path.exists(ccsdt.LIB_PATH):
+        from paper_1609_08094_amd import build
+        build.build()
+    return ccsdt.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ccsdt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for n in ("ccsdt_triples_energy", "ccsdt_energy", "ccsdt_energy_batched", "ccsdt_triple_energies",
+              "ccsdt_debug_w", "ccsdt_context_create", "ccsdt_context_destroy", "ccsdt_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) <= set(ccsdt.EXPORTS) | {"ccsdt_flops"}
+
+
+def test_flops_formula():
+    lib = _lib()
+    for o, v in [(6, 30), (20, 200), (40, 600)]:
+        assert lib.ccsdt_flops(o, v) == pytest.approx((o ** 3 - o) * (2 * v ** 4 + 2 * o * v ** 3), rel=1e-15)
+
+
+def test_null_arguments_are_rejected_without_a_device():
+    lib = _lib()
+    assert lib.ccsdt_context_create(None) == -1
+    assert "null" in lib.ccsdt_last_error().decode()
+    assert lib.ccsdt_context_destroy(None) == -1
+    out = (ctypes.c_double * 3)()
+    assert lib.ccsdt_energy(None, None, 0, None, out) == -1
+    assert lib.ccsdt_triples_energy(6, 30, *([None] * 7), 0, None, None) == -1
+    assert lib.ccsdt_profile_get(None, 0, None, None) == -1
