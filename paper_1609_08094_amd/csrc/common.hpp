@@ -57,11 +57,15 @@ hipError_t launch_final_reduce(const int* d_trip_begin, int nprob, const double*
 // W (any precision) of one slot widened to float64.
 hipError_t launch_widen_w(int prec, const void* w, int64_t n, double* out, hipStream_t s);
 
-// Contraction tile configurations: wave tile (16*WM) x (16*WN), 2x2 waves.
-struct TileCfg { int wm, wn; };
-constexpr int NTILE_CFG = 3;
-constexpr TileCfg TILE_CFGS[NTILE_CFG] = {{2, 2}, {4, 2}, {4, 4}};
-inline int tile_m(int cfg) { return 32 * TILE_CFGS[cfg].wm; }
-inline int tile_n(int cfg) { return 32 * TILE_CFGS[cfg].wn; }
+// Contraction tile configurations (workgroup tile BM x BN over the (row, col)
+// plane of one batch index).  0-2: operands loaded straight from global
+// memory into MFMA fragments, 2x2 waves.  3-5: operands staged through
+// double-buffered LDS, 2x2 waves.
+struct TileCfg { int bm, bn, lds; };
+constexpr int NTILE_CFG = 6;
+constexpr TileCfg TILE_CFGS[NTILE_CFG] = {
+    {64, 64, 0}, {128, 64, 0}, {128, 128, 0}, {128, 128, 1}, {128, 256, 1}, {64, 128, 1}};
+inline int tile_m(int cfg) { return TILE_CFGS[cfg].bm; }
+inline int tile_n(int cfg) { return TILE_CFGS[cfg].bn; }
 
 }  // namespace ccsdt

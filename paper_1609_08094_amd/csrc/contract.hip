@@ -31,6 +31,7 @@ namespace ccsdt {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // HIP uint4 blocks scalar replacement
 
 // Workgroups are dispatched round-robin over the XCDs; give each XCD a
 // contiguous range of logical work so tiles sharing operand rows share an L2.
@@ -51,6 +52,12 @@ struct PrecF64 {
     static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
         f.x = *reinterpret_cast<const f64x4*>(row + c * 16 + 4 * (lane >> 4));
     }
+    // LDS staging: one k sub-step spans SUB_BYTES of a row; lane group l/16
+    // reads LANE_BYTES of it.
+    static constexpr int SUB_BYTES = 128, LANE_BYTES = 32;
+    static __device__ __forceinline__ void load_lds(Frag& f, const char* p) {
+        f.x = *reinterpret_cast<const f64x4*>(p);
+    }
     static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[0], b.x[0], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[1], b.x[1], acc, 0, 0, 0);
@@ -69,6 +76,10 @@ struct PrecF32 {
     static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
     static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
         f.x = *reinterpret_cast<const f32x4*>(row + c * 16 + 4 * (lane >> 4));
+    }
+    static constexpr int SUB_BYTES = 64, LANE_BYTES = 16;
+    static __device__ __forceinline__ void load_lds(Frag& f, const char* p) {
+        f.x = *reinterpret_cast<const f32x4*>(p);
     }
     static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[0], b.x[0], acc, 0, 0, 0);
@@ -90,6 +101,11 @@ struct PrecB3 {
         const E* p = row + (c * 4 + (lane >> 4)) * 16;
         f.hi = *reinterpret_cast<const bf16x8*>(p);
         f.lo = *reinterpret_cast<const bf16x8*>(p + 8);
+    }
+    static constexpr int SUB_BYTES = 128, LANE_BYTES = 32;
+    static __device__ __forceinline__ void load_lds(Frag& f, const char* p) {
+        f.hi = *reinterpret_cast<const bf16x8*>(p);
+        f.lo = *reinterpret_cast<const bf16x8*>(p + 16);
     }
     static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
@@ -125,12 +141,38 @@ __device__ __forceinline__ SegRows segment(int pass, int s, int i, int j, int k,
     return g;
 }
 
+// Write (pass A) or add (pass B) a wave's accumulator blocks into W[a][b][c].
 template <class P, int WM, int WN>
-__global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ slots, int nslot, int pass,
-                                                       int total) {
-    using E = typename P::E;
+__device__ __forceinline__ void store_tile(const Slot* S, int pass, int beta, int m0, int n0, int vm, int vn,
+                                           int lane, typename P::Acc (&acc)[WM][WN]) {
     using Wt = typename P::W;
-    const int bid = xcd_remap(blockIdx.x, total);
+    const int v = S->v;
+    Wt* out = static_cast<Wt*>(S->w);
+    const int64_t V = v, V2 = (int64_t)v * v;
+    const int64_t oB = pass ? V : V2, oM = pass ? V2 : V;
+#pragma unroll
+    for (int a = 0; a < WM; ++a) {
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+            if (a < vm && b < vn) {
+                const int n = n0 + b * 16 + (lane & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = m0 + a * 16 + P::out_row(lane, r);
+                    if (m < v && n < v) {
+                        const int64_t idx = beta * oB + m * oM + n;
+                        const Wt val = (Wt)acc[a][b][r];
+                        if (pass) out[idx] += val; else out[idx] = val;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Locate this workgroup's slot, batch index and tile.
+__device__ __forceinline__ const Slot* find_slot(const Slot* slots, int nslot, int pass, int bid, int& beta,
+                                                 int& tmi, int& tni) {
     int lo = 0, hi = nslot - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -138,14 +180,25 @@ __global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ 
         if (b <= bid) lo = mid; else hi = mid - 1;
     }
     const Slot* S = slots + lo;
-    const int v = S->v, o = S->o, Kp = S->Kp;
     const int tn = S->tiles_n;
     int local = bid - (pass ? S->b_begin : S->a_begin);
     const int per_beta = S->tiles_m * tn;
-    const int beta = local / per_beta;
+    beta = local / per_beta;
     local -= beta * per_beta;
-    const int tmi = local / tn, tni = local - (local / tn) * tn;
+    tmi = local / tn;
+    tni = local - tmi * tn;
+    return S;
+}
 
+template <class P, int WM, int WN>
+__global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ slots, int nslot, int pass,
+                                                       int total) {
+    using E = typename P::E;
+    using Wt = typename P::W;
+    const int bid = xcd_remap(blockIdx.x, total);
+    int beta, tmi, tni;
+    const Slot* S = find_slot(slots, nslot, pass, bid, beta, tmi, tni);
+    const int v = S->v, o = S->o, Kp = S->Kp;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m0 = tmi * (32 * WM) + (wave >> 1) * (16 * WM);
     const int n0 = tni * (32 * WN) + (wave & 1) * (16 * WN);
@@ -203,27 +256,130 @@ __global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ 
         }
     }
 
-    Wt* out = static_cast<Wt*>(S->w);
-    const int64_t V = v, V2 = (int64_t)v * v;
-    const int64_t oB = pass ? V : V2, oM = pass ? V2 : V;
+    store_tile<P, WM, WN>(S, pass, beta, m0, n0, vm, vn, lane, acc);
+}
+
+// LDS-staged variant.  Each workgroup (2x2 waves, wave tile WTM x WTN)
+// streams its BM + BN operand rows through two LDS stages of ROWB bytes per
+// row (padded by 16 bytes so that the 16 lanes of one fragment read hit
+// distinct banks), one barrier per stage; the next stage is fetched into
+// registers while the current one feeds the MFMAs.
+template <class P, int WTM, int WTN, int ROWB, int MINB>
+__global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __restrict__ slots, int nslot,
+                                                                  int pass, int total) {
+    using E = typename P::E;
+    constexpr int NT = 256;
+    constexpr int BM = 2 * WTM, BN = 2 * WTN;
+    constexpr int RS = ROWB + 16;
+    constexpr int ROWS = BM + BN;
+    constexpr int TPR = ROWB / 16;
+    constexpr int RPP = NT / TPR;
+    constexpr int NP = ROWS / RPP;
+    static_assert(ROWS % RPP == 0, "rows must split evenly over the threads");
+    constexpr int MB = WTM / 16, NB = WTN / 16;
+    constexpr int NSUB = ROWB / P::SUB_BYTES;
+    __shared__ __attribute__((aligned(16))) char lds[2 * ROWS * RS];
+
+    const int bid = xcd_remap(blockIdx.x, total);
+    int beta, tmi, tni;
+    const Slot* S = find_slot(slots, nslot, pass, bid, beta, tmi, tni);
+    const int v = S->v, o = S->o, Kp = S->Kp;
+    const int mt0 = tmi * BM, nt0 = tni * BN;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = mt0 + wm * WTM, n0 = nt0 + wn * WTN;
+    const int vm = max(0, min(MB, (v - m0 + 15) / 16));
+    const int vn = max(0, min(NB, (v - n0 + 15) / 16));
+
+    const int64_t rowbytes = (int64_t)Kp * P::UNITS * sizeof(E);
+    const int csteps = (int)(rowbytes / ROWB);
+    const int nseg = pass ? 2 : 4;
+    const int nsteps = nseg * csteps;
+    const char* G = static_cast<const char*>(S->gc);
+    const char* T = static_cast<const char*>(S->tc);
+    const int lrow = threadIdx.x / TPR, lcol = (threadIdx.x % TPR) * 16;
+
+    // Byte offset of each of this thread's rows for the current segment,
+    // relative to the segment's A or B operand array.
+    int64_t roff[NP];
+    u32x4 st[NP];
+    typename P::Acc acc[MB][NB];
 #pragma unroll
-    for (int a = 0; a < WM; ++a) {
+    for (int a = 0; a < MB; ++a)
 #pragma unroll
-        for (int b = 0; b < WN; ++b) {
-            if (a < vm && b < vn) {
-                const int n = n0 + b * 16 + (lane & 15);
+        for (int b = 0; b < NB; ++b) acc[a][b] = typename P::Acc{};
+
+#define CCSDT_SET_PTRS(sg)                                                          \
+    {                                                                               \
+        const SegRows g_ = segment(pass, (sg), S->i, S->j, S->k, o, v);             \
+        baseA = g_.aG ? G : T;                                                      \
+        baseB = g_.bG ? G : T;                                                      \
+        _Pragma("unroll") for (int p = 0; p < NP; ++p) {                            \
+            const int r = lrow + p * RPP;                                           \
+            if (r < BM) {                                                           \
+                const int m = min(mt0 + r, v - 1);                                  \
+                roff[p] = (g_.a0 + beta * g_.aB + m * g_.aM) * rowbytes + lcol;     \
+            } else {                                                                \
+                const int n = min(nt0 + r - BM, v - 1);                             \
+                roff[p] = (g_.b0 + beta * g_.bB + n * g_.bN) * rowbytes + lcol;     \
+            }                                                                       \
+        }                                                                           \
+    }
+#define CCSDT_GLOAD(c)                                                                         \
+    _Pragma("unroll") for (int p = 0; p < NP; ++p) {                                           \
+        const char* src = ((lrow + p * RPP) < BM ? baseA : baseB) + roff[p] + (int64_t)(c) * ROWB; \
+        st[p] = *reinterpret_cast<const u32x4*>(src);                                          \
+    }
+#define CCSDT_LSTORE(buf)                                                                      \
+    {                                                                                          \
+        char* dst_ = lds + (buf) * (ROWS * RS) + lrow * RS + lcol;                             \
+        _Pragma("unroll") for (int p = 0; p < NP; ++p)                                         \
+            *reinterpret_cast<u32x4*>(dst_ + p * RPP * RS) = st[p];                            \
+    }
+
+    const char* baseA = G;
+    const char* baseB = T;
+    CCSDT_SET_PTRS(0);
+    CCSDT_GLOAD(0);
+    CCSDT_LSTORE(0);
+    __syncthreads();
+    const bool active = vm > 0 && vn > 0;
+    int sg_next = 0, c_next = 0;
+    for (int step = 0; step < nsteps; ++step) {
+        const int buf = step & 1;
+        const bool more = step + 1 < nsteps;
+        if (more) {
+            if (++c_next == csteps) {
+                c_next = 0;
+                ++sg_next;
+                CCSDT_SET_PTRS(sg_next);
+            }
+            CCSDT_GLOAD(c_next);
+        }
+        if (active) {
+            const char* As = lds + buf * (ROWS * RS) + (wm * WTM + (lane & 15)) * RS + (lane >> 4) * P::LANE_BYTES;
+            const char* Bs = lds + buf * (ROWS * RS) + (BM + wn * WTN + (lane & 15)) * RS + (lane >> 4) * P::LANE_BYTES;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int m = m0 + a * 16 + P::out_row(lane, r);
-                    if (m < v && n < v) {
-                        const int64_t idx = beta * oB + m * oM + n;
-                        const Wt val = (Wt)acc[a][b][r];
-                        if (pass) out[idx] += val; else out[idx] = val;
-                    }
-                }
+            for (int sub = 0; sub < NSUB; ++sub) {
+                typename P::Frag fa[MB], fb[NB];
+#pragma unroll
+                for (int a = 0; a < MB; ++a) P::load_lds(fa[a], As + a * 16 * RS + sub * P::SUB_BYTES);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) P::load_lds(fb[b], Bs + b * 16 * RS + sub * P::SUB_BYTES);
+#pragma unroll
+                for (int a = 0; a < MB; ++a)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        if (a < vm && b < vn) P::mma(acc[a][b], fa[a], fb[b]);
             }
         }
+        if (more) CCSDT_LSTORE(buf ^ 1);
+        __syncthreads();
     }
+#undef CCSDT_SET_PTRS
+#undef CCSDT_GLOAD
+#undef CCSDT_LSTORE
+    if (active) store_tile<P, MB, NB>(S, pass, beta, m0, n0, vm, vn, lane, acc);
 }
 
 template <class P>
@@ -232,6 +388,9 @@ static hipError_t contract_impl(int cfg, int pass, const Slot* d_slots, int nslo
         case 0: hipLaunchKernelGGL((contract_kernel<P, 2, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
         case 1: hipLaunchKernelGGL((contract_kernel<P, 4, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
         case 2: hipLaunchKernelGGL((contract_kernel<P, 4, 4>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
+        case 3: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 64, 128, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
+        case 4: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 128, 128, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
+        case 5: hipLaunchKernelGGL((contract_lds_kernel<P, 32, 64, 128, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
