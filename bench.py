@@ -7,11 +7,11 @@ energy kernel and every reduction) over synthetic inputs already resident in
 HBM.  Prints one JSON line.  The metric is algorithmic GFLOP/s, with
 F = (o^3 - o)(2 v^4 + 2 o v^3) the distinct contraction flops under i<=j<=k.
 
-roofline: the dominant kernel is contraction pass A (four of the six
-permutation terms).  Its algorithmic flops per launch are 4/6 of the flops of
-the triples it processes; for BF16X3 every useful multiply-add issues three
-bf16 MFMA products, so the MFMA flops are three times that and are compared
-with the dense bf16 peak.  Durations come from HIP events the library
+roofline: the dominant kernel is the contraction (both passes, all six
+permutation terms of W).  Its algorithmic flops per launch are the flops of
+the triples it processes, m (2 v^4 + 2 o v^3) per triple; for BF16X3 every
+useful multiply-add issues three bf16 MFMA products, so the MFMA flops are
+three times that and are compared with the dense bf16 peak.  Durations come from HIP events the library
 records around every launch on the launch stream.
 
 cpu_baseline: the CPU oracle (test infrastructure) on a fixed sample of
@@ -122,9 +122,9 @@ def main():
     log(f"bench: E={E!r} ms/step={ms:.1f} GFLOP/s={gflops:.1f}")
 
     prof = {name: ctx.profile_get(name) for name in ccsdt.KERNEL_CLASSES}
-    na, ms_a = prof["contract_a"]
+    na, ms_a = prof["contract"]
     avg_a = ms_a / max(na, 1)
-    flops_a_per_launch = (4.0 / 6.0) * F * args.steps / max(na, 1)
+    flops_a_per_launch = F * args.steps / max(na, 1)
     mf = MFMA_FACTOR[args.precision]
     achieved = mf * flops_a_per_launch / (avg_a * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
@@ -163,7 +163,7 @@ def main():
         "mfma_util": achieved / peak,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": "contract pass A", "avg_launch_ms": avg_a, "launches_per_step": na // args.steps},
+                     "kernel": "contraction", "avg_launch_ms": avg_a, "launches_per_step": na // args.steps},
         "kernels": kernels,
         "parity_sample": parity,
         "cpu_baseline": cpu,

@@ -142,8 +142,8 @@ int ccsdt_energy_batched(ccsdt_context* ctx, int nprob, const ccsdt_problem* pro
 /* Kernel timing: when enabled, every launch of each kernel class is bracketed
  * by HIP events on the launch stream, and ccsdt_profile_get returns the
  * number of launches and their summed duration (ms) since the last reset.
- * Classes: 0 pack, 1 contract pass A (four permutation terms), 2 contract
- * pass B (two terms, completes W), 3 energy, 4 reductions. */
+ * Classes: 0 pack, 1 contraction (both passes: the six permutation terms of
+ * W for every triple of a chunk), 2 energy, 3 reductions. */
 int ccsdt_profile_enable(ccsdt_context* ctx, int on);
 int ccsdt_profile_get(ccsdt_context* ctx, int kernel_class, int64_t* launches,
                       double* total_ms);

@@ -17,7 +17,7 @@ FP64, FP32, BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 STATUS = {0: "CCSDT_OK", -1: "CCSDT_EINVAL", -2: "CCSDT_ENOMEM", -3: "CCSDT_EHIP",
           -4: "CCSDT_EUNSUPPORTED", -5: "CCSDT_EDENOM"}
-KERNEL_CLASSES = {"pack": 0, "contract_a": 1, "contract_b": 2, "energy": 3, "reduce": 4}
+KERNEL_CLASSES = {"pack": 0, "contract": 1, "energy": 2, "reduce": 3}
 FIELDS = ("eps_o", "eps_v", "t1", "t2", "vvvo", "ovoo", "ovov")
 EXPORTS = ("ccsdt_context_create", "ccsdt_context_destroy", "ccsdt_energy", "ccsdt_triples_energy",
            "ccsdt_triple_energies", "ccsdt_debug_w", "ccsdt_energy_batched", "ccsdt_profile_enable",

@@ -3,8 +3,8 @@
 // Work list (paper Sec. 3: restricted occupied loops collapsed into one loop
 // of independent tasks, eq. tasks_ccsdpt): the triples i<=j<=k with a
 // non-zero multiplicity.  Triples are processed in chunks whose W buffers fit
-// the W budget; each chunk is four launches:
-//   contract pass A  ->  contract pass B  ->  energy partials  ->  slot reduce
+// the W budget; each chunk is three launches:
+//   contraction (both passes)  ->  energy partials  ->  slot reduce
 // after the operands of every problem have been packed once per call.  A
 // final reduce sums the per-triple energies of each problem in a fixed order.
 #include <hip/hip_runtime.h>
@@ -37,7 +37,7 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
-enum { K_PACK = 0, K_PASSA = 1, K_PASSB = 2, K_ENERGY = 3, K_REDUCE = 4, K_NCLASS = 5 };
+enum { K_PACK = 0, K_CONTRACT = 1, K_ENERGY = 2, K_REDUCE = 3, K_NCLASS = 4 };
 
 size_t env_size(const char* name, size_t dflt) {
     const char* s = std::getenv(name);
@@ -244,7 +244,7 @@ int tile_cfg_for(int prec, int v) {
     int forced = env_int("CCSDT_TILE", -1);
     if (forced >= 0 && forced < NTILE_CFG) return forced;
     (void)prec;
-    return v >= 384 ? 1 : 0;
+    return v >= 64 ? 3 : 0;
 }
 
 struct ProbLayout {
@@ -302,8 +302,8 @@ int run_pipeline(ccsdt_context* ctx, std::vector<ProbLayout>& probs, const std::
             size_t e = b, wsum = 0, psum = 0;
             while (e < trips.size()) {
                 const int64_t v = probs[trips[e].prob].p.nvirt;
-                const size_t wsz = ((size_t)(v * v * v) * wb + 255) / 256 * 256;
-                const int nb = (int)((v + EB - 1) / EB);
+                const int nb = (int)((v + WB - 1) / WB);
+                const size_t wsz = 2 * (size_t)nb * nb * nb * WB * WB * WB * wb;   // W_A and W_B
                 const size_t psz = (size_t)nb * (nb + 1) * (nb + 2) / 6 * 2 * sizeof(double);
                 if (e > b && wsum + wsz > ctx->w_budget) break;
                 if (e > b && probs[trips[e].prob].cfg != probs[trips[b].prob].cfg) break;
@@ -325,10 +325,10 @@ int run_pipeline(ccsdt_context* ctx, std::vector<ProbLayout>& probs, const std::
     CHK(ensure_host((void**)&ctx->host_slots, &ctx->host_slots_bytes, std::max<size_t>(nslot_total, 1) * sizeof(Slot)));
 
     // slot descriptors of every chunk, uploaded once
-    struct ChunkInfo { size_t first, n; int totA, totB, totE; int cfgs; };
+    struct ChunkInfo { size_t first, n; int totA, totE; int cfgs; };
     std::vector<ChunkInfo> cinfo;
     for (auto& ch : chunks) {
-        ChunkInfo ci{ch.first, ch.second - ch.first, 0, 0, 0, -1};
+        ChunkInfo ci{ch.first, ch.second - ch.first, 0, 0, -1};
         size_t woff = 0;
         int64_t poff = 0;
         for (size_t t = ch.first; t < ch.second; ++t) {
@@ -341,18 +341,18 @@ int run_pipeline(ccsdt_context* ctx, std::vector<ProbLayout>& probs, const std::
             S.o = L.p.nocc; S.v = v; S.Kp = L.Kp; S.prob = tr.prob;
             S.tiles_m = (v + tile_m(L.cfg) - 1) / tile_m(L.cfg);
             S.tiles_n = (v + tile_n(L.cfg) - 1) / tile_n(L.cfg);
-            S.nblk = (v + EB - 1) / EB;
-            const int norb = S.nblk * (S.nblk + 1) * (S.nblk + 2) / 6;
-            const int per = v * S.tiles_m * S.tiles_n;
+            S.nbw = (v + WB - 1) / WB;
+            const int norb = S.nbw * (S.nbw + 1) * (S.nbw + 2) / 6;
+            const int per = 2 * v * S.tiles_m * S.tiles_n;   // pass A then pass B
             S.a_begin = ci.totA; ci.totA += per;
-            S.b_begin = ci.totB; ci.totB += per;
+            S.b_begin = S.a_begin;
             S.e_begin = ci.totE; ci.totE += norb;
             S.part_begin = poff; poff += norb;
             S.trip_index = tr.out_index;
             S.gc = static_cast<char*>(ctx->gc.p) + L.gc_off;
             S.tc = static_cast<char*>(ctx->tc.p) + L.tc_off;
             S.w = static_cast<char*>(ctx->w.p) + woff;
-            woff += ((size_t)v * v * v * wb + 255) / 256 * 256;
+            woff += 2 * (size_t)S.nbw * S.nbw * S.nbw * WB * WB * WB * wb;
             S.eps_o = L.p.eps_o; S.eps_v = L.p.eps_v; S.t1 = L.p.t1; S.ovov = L.p.ovov;
             ci.cfgs = L.cfg;  // uniform inside a chunk (chunks break where it changes)
         }
@@ -366,11 +366,10 @@ int run_pipeline(ccsdt_context* ctx, std::vector<ProbLayout>& probs, const std::
         const Slot* d = dslots + ci.first;
         const int n = (int)ci.n;
         const int cfg = ci.cfgs;
-        LAUNCH(K_PASSA, launch_contract(prec, cfg, 0, d, n, ci.totA, s));
-        LAUNCH(K_PASSB, launch_contract(prec, cfg, 1, d, n, ci.totB, s));
+        LAUNCH(K_CONTRACT, launch_contract(prec, cfg, d, n, ci.totA, s));
         if (debug_w) {
             const int v = ctx->host_slots[ci.first].v;
-            LAUNCH(K_REDUCE, launch_widen_w(prec, ctx->host_slots[ci.first].w, (int64_t)v * v * v, debug_w, s));
+            LAUNCH(K_REDUCE, launch_widen_w(prec, ctx->host_slots[ci.first].w, v, debug_w, s));
             continue;
         }
         LAUNCH(K_ENERGY, launch_energy(prec, d, n, ci.totE, part, s));

@@ -9,13 +9,28 @@ namespace ccsdt {
 
 // Packed operand rows are padded with zeros to a multiple of KPAD elements.
 constexpr int KPAD = 32;
-// Edge of the cubic virtual blocks the energy kernel walks (one block orbit
-// per workgroup).
-constexpr int EB = 16;
+// W is stored in cubic blocks of WB^3 elements, block-major:
+//   W[(A*nb + B)*nb + C][a%WB][b%WB][c%WB],  A = a/WB, nb = ceil(v/WB),
+// so that a block of any index order is one contiguous read.  The energy
+// kernel walks orbits of these blocks (one per workgroup) and stages
+// SB^3 sub-blocks through LDS.
+constexpr int WB = 16;
+constexpr int SB = 8;
 // Number of XCDs on MI355X; workgroups are dispatched round-robin over them.
 constexpr int NXCD = 8;
 
 enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16X3 = 2 };
+
+// Pointers read out of the slot table are generic to the compiler, which
+// would then emit flat memory instructions; flat loads share the wait
+// counter of LDS reads and would stall every LDS fragment read on the
+// in-flight global prefetch.  Accesses to HBM go through global-space
+// pointers instead.
+#define GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const GLOBAL T* gp(const T* p) { return (const GLOBAL T*)p; }
+template <class T>
+__device__ __forceinline__ GLOBAL T* gpw(T* p) { return (GLOBAL T*)p; }
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -25,13 +40,13 @@ struct Slot {
     int i, j, k, mult;        // triple and its multiplicity (6 or 3)
     int o, v, Kp, prob;       // sizes and problem index
     int tiles_m, tiles_n;     // ceil(v / tile edge) along m and n
-    int nblk, pad_;           // energy blocks per dimension
-    int a_begin, b_begin;     // first workgroup of this slot in pass A / pass B
+    int nbw, pad_;            // W blocks per dimension, ceil(v / WB)
+    int a_begin, b_begin;     // first contraction workgroup of this slot; unused
     int e_begin, trip_index;  // first energy workgroup; index into e_trip
     int64_t part_begin;       // first partial-sum entry (2 doubles each)
     const void* gc;           // packed [p][x][y][Kp] operand of the problem
     const void* tc;           // packed [r][q][z][Kp] operand of the problem
-    void* w;                  // W[a][b][c] of this slot (v^3 elements)
+    void* w;                  // W_A then W_B of this slot (2 nbw^3 WB^3 elements)
     const double* eps_o;
     const double* eps_v;
     const double* t1;
@@ -42,9 +57,8 @@ struct Slot {
 // Pack one problem's operands into the precision's layout (see pack.hip).
 hipError_t launch_pack(int prec, int o, int v, int Kp, const double* vvvo, const double* t2,
                        const double* ovoo, void* gc, void* tc, hipStream_t s);
-// Contraction pass A (pass=0) or B (pass=1) over the slots of a chunk.
-hipError_t launch_contract(int prec, int tile_cfg, int pass, const Slot* d_slots, int nslot,
-                           int total_wg, hipStream_t s);
+// Both contraction passes over the slots of a chunk (one launch).
+hipError_t launch_contract(int prec, int tile_cfg, const Slot* d_slots, int nslot, int total_wg, hipStream_t s);
 // Energy partials over the block orbits of every slot.
 hipError_t launch_energy(int prec, const Slot* d_slots, int nslot, int total_wg,
                          double* partials, hipStream_t s);
@@ -54,8 +68,12 @@ hipError_t launch_slot_reduce(const Slot* d_slots, int nslot, int norb_max_unuse
 // Per-problem deterministic sum of e_trip ranges into out[3*p].
 hipError_t launch_final_reduce(const int* d_trip_begin, int nprob, const double* e_trip,
                                double* out, hipStream_t s);
-// W (any precision) of one slot widened to float64.
-hipError_t launch_widen_w(int prec, const void* w, int64_t n, double* out, hipStream_t s);
+// W (any precision, blocked layout) of one slot as dense float64 [a][b][c].
+hipError_t launch_widen_w(int prec, const void* w, int v, double* out, hipStream_t s);
+
+__host__ __device__ inline int64_t w_index(int a, int b, int c, int nb) {
+    return ((((int64_t)(a >> 4) * nb + (b >> 4)) * nb + (c >> 4)) << 12) + ((a & 15) << 8) + ((b & 15) << 4) + (c & 15);
+}
 
 // Contraction tile configurations (workgroup tile BM x BN over the (row, col)
 // plane of one batch index).  0-2: operands loaded straight from global

@@ -4,17 +4,17 @@
 // With the packed rows of pack.hip, X^xyz_pqr = <G[p][x][y], T[r][q][z]> and
 //   W^abc_ijk = X^abc_ijk + X^acb_ikj + X^bac_jik + X^bca_jki + X^cab_kij + X^cba_kji.
 // Each term is a batched NT product: one of the two G indices is a batch
-// index, the other the MFMA row, and the T index the MFMA column.  Four terms
-// can be oriented as (row=b, col=c) at fixed a; the two whose T index is a
-// cannot, and are oriented (row=a, col=c) at fixed b:
+// index, the other the MFMA row, and the T index the MFMA column.  Two
+// orientations cover all six terms with three segments each:
 //
-//  pass A, batch a, tile (b,c):  W  = <G_i[a][b],T_kj[c]> + <T_jk[b],G_i[a][c]>
-//                                   + <G_j[b][a],T_ki[c]> + <T_ji[b],G_k[c][a]>
-//  pass B, batch b, tile (a,c):  W += <T_ik[a],G_j[b][c]> + <T_ij[a],G_k[c][b]>
+//  pass A, batch a, tile (b,c):  W_A = <G_i[a][b],T_kj[c]> + <T_jk[b],G_i[a][c]> + <T_ji[b],G_k[c][a]>
+//  pass B, batch b, tile (a,c):  W_B = <G_j[b][a],T_ki[c]> + <T_ik[a],G_j[b][c]> + <T_ij[a],G_k[c][b]>
 //
-// so every W element is written once by pass A and updated once by pass B;
-// the four (two) terms of a pass run as one K loop over 4 (2) segments of
-// length Kp.  Output is W[a][b][c] (FP64 for the FP64 path, FP32 otherwise).
+// W = W_A + W_B.  The two passes are independent (one launch covers both),
+// each writes its own buffer once, and the energy kernel adds the two when
+// it stages W.  The three terms of a pass run as one K loop over three
+// segments of length Kp.  W_A and W_B are FP64 for the FP64 path and FP32
+// otherwise, in the WB^3-blocked layout of common.hpp.
 //
 // MFMA shapes (all with a 16x16 output block; lane l holds four rows of
 // column l%16: rows l/16 + 4r for the FP64 instruction, 4(l/16) + r for the
@@ -50,7 +50,7 @@ struct PrecF64 {
     struct Frag { f64x4 x; };
     static __device__ __forceinline__ int out_row(int lane, int r) { return (lane >> 4) + 4 * r; }
     static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
-        f.x = *reinterpret_cast<const f64x4*>(row + c * 16 + 4 * (lane >> 4));
+        f.x = *reinterpret_cast<const GLOBAL f64x4*>(gp(row + c * 16 + 4 * (lane >> 4)));
     }
     // LDS staging: one k sub-step spans SUB_BYTES of a row; lane group l/16
     // reads LANE_BYTES of it.
@@ -75,7 +75,7 @@ struct PrecF32 {
     struct Frag { f32x4 x; };
     static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
     static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
-        f.x = *reinterpret_cast<const f32x4*>(row + c * 16 + 4 * (lane >> 4));
+        f.x = *reinterpret_cast<const GLOBAL f32x4*>(gp(row + c * 16 + 4 * (lane >> 4)));
     }
     static constexpr int SUB_BYTES = 64, LANE_BYTES = 16;
     static __device__ __forceinline__ void load_lds(Frag& f, const char* p) {
@@ -98,9 +98,9 @@ struct PrecB3 {
     struct Frag { bf16x8 hi, lo; };
     static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
     static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
-        const E* p = row + (c * 4 + (lane >> 4)) * 16;
-        f.hi = *reinterpret_cast<const bf16x8*>(p);
-        f.lo = *reinterpret_cast<const bf16x8*>(p + 8);
+        const GLOBAL E* p = gp(row + (c * 4 + (lane >> 4)) * 16);
+        f.hi = *reinterpret_cast<const GLOBAL bf16x8*>(p);
+        f.lo = *reinterpret_cast<const GLOBAL bf16x8*>(p + 8);
     }
     static constexpr int SUB_BYTES = 128, LANE_BYTES = 32;
     static __device__ __forceinline__ void load_lds(Frag& f, const char* p) {
@@ -129,27 +129,28 @@ __device__ __forceinline__ SegRows segment(int pass, int s, int i, int j, int k,
         switch (s) {
             case 0: g = {i * V2, V, 1, trow(k, j), 0, 1, true, false}; break;   // G_i[a][b] . T_kj[c]
             case 1: g = {trow(j, k), 0, 1, i * V2, V, 1, false, true}; break;   // T_jk[b] . G_i[a][c]
-            case 2: g = {j * V2, 1, V, trow(k, i), 0, 1, true, false}; break;   // G_j[b][a] . T_ki[c]
             default: g = {trow(j, i), 0, 1, k * V2, 1, V, false, true}; break;  // T_ji[b] . G_k[c][a]
         }
     } else {  // batch b, row a, col c
         switch (s) {
-            case 0: g = {trow(i, k), 0, 1, j * V2, V, 1, false, true}; break;   // T_ik[a] . G_j[b][c]
+            case 0: g = {j * V2, V, 1, trow(k, i), 0, 1, true, false}; break;   // G_j[b][a] . T_ki[c]
+            case 1: g = {trow(i, k), 0, 1, j * V2, V, 1, false, true}; break;   // T_ik[a] . G_j[b][c]
             default: g = {trow(i, j), 0, 1, k * V2, 1, V, false, true}; break;  // T_ij[a] . G_k[c][b]
         }
     }
     return g;
 }
 
-// Write (pass A) or add (pass B) a wave's accumulator blocks into W[a][b][c].
+constexpr int NSEG = 3;  // segments per pass
+
+// Store a wave's accumulator blocks into W_A (pass A) or W_B (pass B).
 template <class P, int WM, int WN>
 __device__ __forceinline__ void store_tile(const Slot* S, int pass, int beta, int m0, int n0, int vm, int vn,
                                            int lane, typename P::Acc (&acc)[WM][WN]) {
     using Wt = typename P::W;
     const int v = S->v;
-    Wt* out = static_cast<Wt*>(S->w);
-    const int64_t V = v, V2 = (int64_t)v * v;
-    const int64_t oB = pass ? V : V2, oM = pass ? V2 : V;
+    const int nb = S->nbw;
+    GLOBAL Wt* out = gpw(static_cast<Wt*>(S->w)) + (pass ? (int64_t)nb * nb * nb * (WB * WB * WB) : 0);
 #pragma unroll
     for (int a = 0; a < WM; ++a) {
 #pragma unroll
@@ -160,9 +161,9 @@ __device__ __forceinline__ void store_tile(const Slot* S, int pass, int beta, in
                 for (int r = 0; r < 4; ++r) {
                     const int m = m0 + a * 16 + P::out_row(lane, r);
                     if (m < v && n < v) {
-                        const int64_t idx = beta * oB + m * oM + n;
-                        const Wt val = (Wt)acc[a][b][r];
-                        if (pass) out[idx] += val; else out[idx] = val;
+                        // pass A: (a,b,c) = (beta, m, n); pass B: (m, beta, n)
+                        const int64_t idx = pass ? w_index(m, beta, n, nb) : w_index(beta, m, n, nb);
+                        out[idx] = (Wt)acc[a][b][r];
                     }
                 }
             }
@@ -170,19 +171,22 @@ __device__ __forceinline__ void store_tile(const Slot* S, int pass, int beta, in
     }
 }
 
-// Locate this workgroup's slot, batch index and tile.
-__device__ __forceinline__ const Slot* find_slot(const Slot* slots, int nslot, int pass, int bid, int& beta,
+// Locate this workgroup's slot, pass, batch index and tile.  Within a slot
+// the pass-A workgroups come first, then the pass-B ones.
+__device__ __forceinline__ const Slot* find_slot(const Slot* slots, int nslot, int bid, int& pass, int& beta,
                                                  int& tmi, int& tni) {
     int lo = 0, hi = nslot - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const int b = pass ? slots[mid].b_begin : slots[mid].a_begin;
-        if (b <= bid) lo = mid; else hi = mid - 1;
+        if (slots[mid].a_begin <= bid) lo = mid; else hi = mid - 1;
     }
     const Slot* S = slots + lo;
     const int tn = S->tiles_n;
-    int local = bid - (pass ? S->b_begin : S->a_begin);
     const int per_beta = S->tiles_m * tn;
+    int local = bid - S->a_begin;
+    const int per_pass = S->v * per_beta;
+    pass = local >= per_pass;
+    local -= pass * per_pass;
     beta = local / per_beta;
     local -= beta * per_beta;
     tmi = local / tn;
@@ -191,13 +195,12 @@ __device__ __forceinline__ const Slot* find_slot(const Slot* slots, int nslot, i
 }
 
 template <class P, int WM, int WN>
-__global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ slots, int nslot, int pass,
-                                                       int total) {
+__global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ slots, int nslot, int total) {
     using E = typename P::E;
     using Wt = typename P::W;
     const int bid = xcd_remap(blockIdx.x, total);
-    int beta, tmi, tni;
-    const Slot* S = find_slot(slots, nslot, pass, bid, beta, tmi, tni);
+    int pass, beta, tmi, tni;
+    const Slot* S = find_slot(slots, nslot, bid, pass, beta, tmi, tni);
     const int v = S->v, o = S->o, Kp = S->Kp;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m0 = tmi * (32 * WM) + (wave >> 1) * (16 * WM);
@@ -215,7 +218,7 @@ __global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ 
     const int64_t rl = (int64_t)Kp * P::UNITS;
     const E* G = static_cast<const E*>(S->gc);
     const E* T = static_cast<const E*>(S->tc);
-    const int nseg = pass ? 2 : 4;
+    const int nseg = NSEG;
     const int nch = Kp / P::KCH;
     for (int s = 0; s < nseg; ++s) {
         const SegRows g = segment(pass, s, S->i, S->j, S->k, o, v);
@@ -259,6 +262,26 @@ __global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ 
     store_tile<P, WM, WN>(S, pass, beta, m0, n0, vm, vn, lane, acc);
 }
 
+// MFMAs over one LDS stage for a wave's MB x NB blocks.  FULL skips the
+// per-block edge tests (interior tiles), keeping the MFMA stream branch-free.
+template <class P, int MB, int NB, int NSUB, int RS, bool FULL>
+__device__ __forceinline__ void lds_stage(typename P::Acc (&acc)[MB][NB], const char* As, const char* Bs, int vm,
+                                          int vn) {
+#pragma unroll
+    for (int sub = 0; sub < NSUB; ++sub) {
+        typename P::Frag fa[MB], fb[NB];
+#pragma unroll
+        for (int a = 0; a < MB; ++a) P::load_lds(fa[a], As + a * 16 * RS + sub * P::SUB_BYTES);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) P::load_lds(fb[b], Bs + b * 16 * RS + sub * P::SUB_BYTES);
+#pragma unroll
+        for (int a = 0; a < MB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if (FULL || (a < vm && b < vn)) P::mma(acc[a][b], fa[a], fb[b]);
+    }
+}
+
 // LDS-staged variant.  Each workgroup (2x2 waves, wave tile WTM x WTN)
 // streams its BM + BN operand rows through two LDS stages of ROWB bytes per
 // row (padded by 16 bytes so that the 16 lanes of one fragment read hit
@@ -266,7 +289,7 @@ __global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ 
 // registers while the current one feeds the MFMAs.
 template <class P, int WTM, int WTN, int ROWB, int MINB>
 __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __restrict__ slots, int nslot,
-                                                                  int pass, int total) {
+                                                                  int total) {
     using E = typename P::E;
     constexpr int NT = 256;
     constexpr int BM = 2 * WTM, BN = 2 * WTN;
@@ -281,8 +304,8 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
     __shared__ __attribute__((aligned(16))) char lds[2 * ROWS * RS];
 
     const int bid = xcd_remap(blockIdx.x, total);
-    int beta, tmi, tni;
-    const Slot* S = find_slot(slots, nslot, pass, bid, beta, tmi, tni);
+    int pass, beta, tmi, tni;
+    const Slot* S = find_slot(slots, nslot, bid, pass, beta, tmi, tni);
     const int v = S->v, o = S->o, Kp = S->Kp;
     const int mt0 = tmi * BM, nt0 = tni * BN;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -293,8 +316,7 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
 
     const int64_t rowbytes = (int64_t)Kp * P::UNITS * sizeof(E);
     const int csteps = (int)(rowbytes / ROWB);
-    const int nseg = pass ? 2 : 4;
-    const int nsteps = nseg * csteps;
+    const int nsteps = NSEG * csteps;
     const char* G = static_cast<const char*>(S->gc);
     const char* T = static_cast<const char*>(S->tc);
     const int lrow = threadIdx.x / TPR, lcol = (threadIdx.x % TPR) * 16;
@@ -328,7 +350,7 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
 #define CCSDT_GLOAD(c)                                                                         \
     _Pragma("unroll") for (int p = 0; p < NP; ++p) {                                           \
         const char* src = ((lrow + p * RPP) < BM ? baseA : baseB) + roff[p] + (int64_t)(c) * ROWB; \
-        st[p] = *reinterpret_cast<const u32x4*>(src);                                          \
+        st[p] = *reinterpret_cast<const GLOBAL u32x4*>(gp(src));                               \
     }
 #define CCSDT_LSTORE(buf)                                                                      \
     {                                                                                          \
@@ -359,19 +381,10 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
         if (active) {
             const char* As = lds + buf * (ROWS * RS) + (wm * WTM + (lane & 15)) * RS + (lane >> 4) * P::LANE_BYTES;
             const char* Bs = lds + buf * (ROWS * RS) + (BM + wn * WTN + (lane & 15)) * RS + (lane >> 4) * P::LANE_BYTES;
-#pragma unroll
-            for (int sub = 0; sub < NSUB; ++sub) {
-                typename P::Frag fa[MB], fb[NB];
-#pragma unroll
-                for (int a = 0; a < MB; ++a) P::load_lds(fa[a], As + a * 16 * RS + sub * P::SUB_BYTES);
-#pragma unroll
-                for (int b = 0; b < NB; ++b) P::load_lds(fb[b], Bs + b * 16 * RS + sub * P::SUB_BYTES);
-#pragma unroll
-                for (int a = 0; a < MB; ++a)
-#pragma unroll
-                    for (int b = 0; b < NB; ++b)
-                        if (a < vm && b < vn) P::mma(acc[a][b], fa[a], fb[b]);
-            }
+            if (vm == MB && vn == NB)
+                lds_stage<P, MB, NB, NSUB, RS, true>(acc, As, Bs, vm, vn);
+            else
+                lds_stage<P, MB, NB, NSUB, RS, false>(acc, As, Bs, vm, vn);
         }
         if (more) CCSDT_LSTORE(buf ^ 1);
         __syncthreads();
@@ -383,25 +396,25 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
 }
 
 template <class P>
-static hipError_t contract_impl(int cfg, int pass, const Slot* d_slots, int nslot, int total, hipStream_t s) {
+static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int total, hipStream_t s) {
     switch (cfg) {
-        case 0: hipLaunchKernelGGL((contract_kernel<P, 2, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
-        case 1: hipLaunchKernelGGL((contract_kernel<P, 4, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
-        case 2: hipLaunchKernelGGL((contract_kernel<P, 4, 4>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
-        case 3: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 64, 128, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
-        case 4: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 128, 128, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
-        case 5: hipLaunchKernelGGL((contract_lds_kernel<P, 32, 64, 128, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, pass, total); break;
+        case 0: hipLaunchKernelGGL((contract_kernel<P, 2, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 1: hipLaunchKernelGGL((contract_kernel<P, 4, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 2: hipLaunchKernelGGL((contract_kernel<P, 4, 4>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 3: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 64, 128, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 4: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 128, 128, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 5: hipLaunchKernelGGL((contract_lds_kernel<P, 32, 64, 128, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_contract(int prec, int cfg, int pass, const Slot* d_slots, int nslot, int total, hipStream_t s) {
+hipError_t launch_contract(int prec, int cfg, const Slot* d_slots, int nslot, int total, hipStream_t s) {
     if (total <= 0) return hipSuccess;
     switch (prec) {
-        case P_FP64: return contract_impl<PrecF64>(cfg, pass, d_slots, nslot, total, s);
-        case P_FP32: return contract_impl<PrecF32>(cfg, pass, d_slots, nslot, total, s);
-        case P_BF16X3: return contract_impl<PrecB3>(cfg, pass, d_slots, nslot, total, s);
+        case P_FP64: return contract_impl<PrecF64>(cfg, d_slots, nslot, total, s);
+        case P_FP32: return contract_impl<PrecF32>(cfg, d_slots, nslot, total, s);
+        case P_BF16X3: return contract_impl<PrecB3>(cfg, d_slots, nslot, total, s);
         default: return hipErrorInvalidValue;
     }
 }

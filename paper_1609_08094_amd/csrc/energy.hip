@@ -15,12 +15,41 @@
 // (s = 2 when exactly two of a,b,c are equal; a=b=c contributes exactly 0).
 // E[4] takes V = W, E[5] takes V = Z; E = E[4] + E[5].
 //
-// One workgroup handles one block orbit (A <= B <= C) of EB^3 virtual
-// blocks and visits each representative a <= b <= c once.  Per-workgroup
-// partials go to fixed slots; sums run in a fixed order (deterministic).
+// One workgroup (two waves) handles one orbit (A <= B <= C) of WB^3 blocks
+// of W.  The waves take turns over the SB^3 sub-block orbits (x <= y <= z)
+// inside it.  For each, a wave first issues every load it needs at once --
+// the six permuted sub-blocks W[x][y][z], W[x][z][y], ..., W[z][y][x]
+// (contiguous rows of the blocked layout, W = W_A + W_B summed on the way),
+// the 18 SB x SB sub-blocks of the
+// ovov slices (jX|kY), (iX|kY), (iX|jY) over ordered pairs of {x,y,z}, and
+// the t1 / eps_v segments -- parks them in padded LDS, and then evaluates the
+// representatives a <= b <= c of its (b, c) column from LDS alone.
+// Per-workgroup partials go to fixed slots; sums run in a fixed order
+// (deterministic).
 #include "common.hpp"
 
 namespace ccsdt {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int EW = 2;  // waves per energy workgroup
+
+// W = W_A + W_B for one 16-byte pair of global loads, scattered into padded
+// (unaligned) LDS elements.  The sum is one rounding in the W precision.
+template <class WT> struct Unpack;
+template <> struct Unpack<float> {
+    static __device__ __forceinline__ void put2(float* d, u32x4 x, u32x4 y) {
+        d[0] = __uint_as_float(x.x) + __uint_as_float(y.x);
+        d[1] = __uint_as_float(x.y) + __uint_as_float(y.y);
+        d[2] = __uint_as_float(x.z) + __uint_as_float(y.z);
+        d[3] = __uint_as_float(x.w) + __uint_as_float(y.w);
+    }
+};
+template <> struct Unpack<double> {
+    static __device__ __forceinline__ void put2(double* d, u32x4 x, u32x4 y) {
+        d[0] = __hiloint2double((int)x.y, (int)x.x) + __hiloint2double((int)y.y, (int)y.x);
+        d[1] = __hiloint2double((int)x.w, (int)x.z) + __hiloint2double((int)y.w, (int)y.z);
+    }
+};
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -28,7 +57,7 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
-// Sum x over the 256 threads of the block; valid in thread 0.
+// Sum x over the EW*64 threads of the block; valid in thread 0.
 __device__ __forceinline__ double block_sum(double x, double* sh) {
     x = wave_sum(x);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -36,7 +65,8 @@ __device__ __forceinline__ double block_sum(double x, double* sh) {
     if (lane == 0) sh[wave] = x;
     __syncthreads();
     double r = 0.0;
-    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
     return r;
 }
 
@@ -53,9 +83,19 @@ __device__ __forceinline__ void decode_orbit(int q, int& A, int& B, int& C) {
 }
 
 template <class WT>
-__global__ __launch_bounds__(256) void energy_kernel(const Slot* __restrict__ slots, int nslot,
-                                                     double* __restrict__ partials) {
-    __shared__ double sh[4];
+__global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict__ slots, int nslot,
+                                                         double* __restrict__ partials) {
+    constexpr int RS = SB + 1;            // padded W row (elements)
+    constexpr int PS = SB * RS + 1;       // padded W plane
+    constexpr int BLK = SB * PS;          // one W sub-block
+    constexpr int SRS = SB + 1;           // padded S row (doubles)
+    constexpr int SBLK = SB * SRS;        // one S sub-block
+    constexpr int VPR = 16 / sizeof(WT);  // W elements per 16-byte load
+    constexpr int NVL = SB / VPR;         // 16-byte loads per W row
+    __shared__ WT lw[EW][6][BLK];
+    __shared__ double ls[EW][18][SBLK];
+    __shared__ double lt[EW][4][3][SB];   // t1_i, t1_j, t1_k, eps_v over sub-blocks x, y, z
+    __shared__ double sh[EW];
     const int bid = blockIdx.x;
     int lo = 0, hi = nslot - 1;
     while (lo < hi) {
@@ -66,55 +106,138 @@ __global__ __launch_bounds__(256) void energy_kernel(const Slot* __restrict__ sl
     const int q = bid - S->e_begin;
     int A, B, C;
     decode_orbit(q, A, B, C);
-    const int v = S->v, o = S->o, i = S->i, j = S->j, k = S->k;
-    const WT* W = static_cast<const WT*>(S->w);
-    const double* ev = S->eps_v;
-    const double eo = S->eps_o[i] + S->eps_o[j] + S->eps_o[k];
-    const double* t1i = S->t1 + (int64_t)i * v;
-    const double* t1j = S->t1 + (int64_t)j * v;
-    const double* t1k = S->t1 + (int64_t)k * v;
-    // (pX|qY) = ovov[p][X][q][Y]; rows of the three slices used by Z
+    const int v = S->v, o = S->o, i = S->i, j = S->j, k = S->k, nb = S->nbw;
+    const GLOBAL WT* W = gp(static_cast<const WT*>(S->w));                 // W_A
+    const GLOBAL WT* WBp = W + (int64_t)nb * nb * nb * (WB * WB * WB);       // W_B
+    const GLOBAL double* eps_o = gp(S->eps_o);
+    const double eo = eps_o[i] + eps_o[j] + eps_o[k];
+    // (pX|qY) = ovov[p][X][q][Y]; Spq[X * rs + Y] = (pX|qY)
     const double* ov = S->ovov;
-    const int64_t rs = (int64_t)o * v;  // stride of X in ovov[p][X][q][:]
-    const double* Sjk = ov + ((int64_t)j * v * o + k) * v;  // Sjk[y*rs + z] = (jy|kz)
-    const double* Sik = ov + ((int64_t)i * v * o + k) * v;
-    const double* Sij = ov + ((int64_t)i * v * o + j) * v;
+    const int64_t rs = (int64_t)o * v;
+    const GLOBAL double* S0 = gp(ov + ((int64_t)j * v * o + k) * v);   // (jX|kY)
+    const GLOBAL double* S1 = gp(ov + ((int64_t)i * v * o + k) * v);   // (iX|kY)
+    const GLOBAL double* S2 = gp(ov + ((int64_t)i * v * o + j) * v);   // (iX|jY)
+    const GLOBAL double* T0 = gp(S->t1 + (int64_t)i * v);
+    const GLOBAL double* T1 = gp(S->t1 + (int64_t)j * v);
+    const GLOBAL double* T2 = gp(S->t1 + (int64_t)k * v);
+    const GLOBAL double* ev = gp(S->eps_v);
     const double scale = (double)S->mult / 3.0;
-    const int64_t V = v;
+    const int nsb = (v + SB - 1) / SB;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    WT(*L)[BLK] = lw[wave];
+    double(*LS)[SBLK] = ls[wave];
+    double(*LT)[3][SB] = lt[wave];
 
-    const int c = C * EB + (threadIdx.x & 15);
-    const int b = B * EB + (threadIdx.x >> 4);
     double e4 = 0.0, e5 = 0.0;
-    if (c < v && b <= c) {
-        const double evbc = ev[b] + ev[c];
-        for (int aa = 0; aa < EB; ++aa) {
-            const int a = A * EB + aa;
-            if (a > b) break;
-            if (a == c) continue;  // a = b = c
-            const double w0 = (double)W[(a * V + b) * V + c];
-            const double w1 = (double)W[(a * V + c) * V + b];
-            const double w2 = (double)W[(b * V + a) * V + c];
-            const double w3 = (double)W[(b * V + c) * V + a];
-            const double w4 = (double)W[(c * V + a) * V + b];
-            const double w5 = (double)W[(c * V + b) * V + a];
-            // Z(x,y,z) = t1[i][x] (jy|kz) + t1[j][y] (ix|kz) + t1[k][z] (ix|jy)
-            auto Z = [&](int x, int y, int z) {
-                return t1i[x] * Sjk[y * rs + z] + t1j[y] * Sik[x * rs + z] + t1k[z] * Sij[x * rs + y];
-            };
-            const double z0 = Z(a, b, c), z1 = Z(a, c, b), z2 = Z(b, a, c);
-            const double z3 = Z(b, c, a), z4 = Z(c, a, b), z5 = Z(c, b, a);
-            const double We = w0 + w3 + w4, Wo = w1 + w2 + w5;
-            const double Ze = z0 + z3 + z4, Zo = z1 + z2 + z5;
-            const double sww = w0 * w0 + w1 * w1 + w2 * w2 + w3 * w3 + w4 * w4 + w5 * w5;
-            const double swz = w0 * z0 + w1 * z1 + w2 * z2 + w3 * z3 + w4 * z4 + w5 * z5;
-            const double f4 = 3.0 * sww + We * (We - 2.0 * Wo) + Wo * (Wo - 2.0 * We);
-            const double f5 = 3.0 * swz + We * (Ze - 2.0 * Zo) + Wo * (Zo - 2.0 * Ze);
-            const double D = eo - ev[a] - evbc;
-            const double rep = (a == b || b == c) ? 2.0 : 1.0;
-            const double sc = scale / (rep * D);
-            e4 += f4 * sc;
-            e5 += f5 * sc;
+    for (int it = 0; it < 8 / EW; ++it) {
+        const int s = wave + EW * it;
+        const int x = 2 * A + ((s >> 2) & 1), y = 2 * B + ((s >> 1) & 1), z = 2 * C + (s & 1);
+        const bool ok = x <= y && y <= z && z < nsb;
+        if (ok) {
+            const int r = lane >> 3, cc = lane & 7;
+            // W sub-blocks, order q: (x,y,z) (x,z,y) (y,x,z) (y,z,x) (z,x,y) (z,y,x)
+            const int P[6][3] = {{x, y, z}, {x, z, y}, {y, x, z}, {y, z, x}, {z, x, y}, {z, y, x}};
+            u32x4 wa[6][NVL], wb[6][NVL];
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const int ga = min(SB * P[p][0] + r, v - 1), gb = min(SB * P[p][1] + cc, v - 1);
+                const int64_t off = w_index(ga, gb, SB * P[p][2], nb);
+                const GLOBAL u32x4* srcA = (const GLOBAL u32x4*)(W + off);
+                const GLOBAL u32x4* srcB = (const GLOBAL u32x4*)(WBp + off);
+#pragma unroll
+                for (int g = 0; g < NVL; ++g) {
+                    wa[p][g] = srcA[g];
+                    wb[p][g] = srcB[g];
+                }
+            }
+            // S sub-blocks: index pq*6 + qq, pairs qq: (y,z) (z,y) (x,z) (z,x) (x,y) (y,x)
+            const int QP[6][2] = {{y, z}, {z, y}, {x, z}, {z, x}, {x, y}, {y, x}};
+            double sv[18];
+#pragma unroll
+            for (int qq = 0; qq < 6; ++qq) {
+                const int64_t off = (int64_t)min(SB * QP[qq][0] + r, v - 1) * rs + min(SB * QP[qq][1] + cc, v - 1);
+                sv[qq] = S0[off];
+                sv[6 + qq] = S1[off];
+                sv[12 + qq] = S2[off];
+            }
+            // t1_i, t1_j, t1_k, eps_v over sub-blocks x, y, z: entry e = vec*24 + blk*8 + off
+            double tv[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int e = lane + 64 * h;
+                double val = 0.0;
+                if (e < 96) {
+                    const int vec = e / 24, blk = (e / SB) % 3, off = e % SB;
+                    const int xb = blk == 0 ? x : (blk == 1 ? y : z);
+                    const int g = min(SB * xb + off, v - 1);
+                    const GLOBAL double* src = vec == 0 ? T0 : (vec == 1 ? T1 : (vec == 2 ? T2 : ev));
+                    val = src[g];
+                }
+                tv[h] = val;
+            }
+#pragma unroll
+            for (int p = 0; p < 6; ++p)
+#pragma unroll
+                for (int g = 0; g < NVL; ++g) Unpack<WT>::put2(&L[p][r * PS + cc * RS + g * VPR], wa[p][g], wb[p][g]);
+#pragma unroll
+            for (int n = 0; n < 18; ++n) LS[n][r * SRS + cc] = sv[n];
+            (&LT[0][0][0])[lane] = tv[0];
+            if (lane < 32) (&LT[0][0][0])[lane + 64] = tv[1];
         }
+        __syncthreads();
+        if (ok) {
+            const int be = lane >> 3, ga = lane & 7;   // (beta, gamma) column of this lane
+            const int b = SB * y + be, c = SB * z + ga;
+            if (b < v && c < v && b <= c) {
+                // LT[vec][blk][off]: vec 0 t1_i, 1 t1_j, 2 t1_k, 3 eps_v; blk 0 x, 1 y, 2 z
+                const double evbc = LT[3][1][be] + LT[3][2][ga];
+                const double t1ib = LT[0][1][be], t1ic = LT[0][2][ga];
+                const double t1jb = LT[1][1][be], t1jc = LT[1][2][ga];
+                const double t1kb = LT[2][1][be], t1kc = LT[2][2][ga];
+                // alpha-independent S entries: Q0 = (y,z), Q1 = (z,y)
+                const double Sjk_bc = LS[0][be * SRS + ga], Sjk_cb = LS[1][ga * SRS + be];
+                const double Sik_bc = LS[6][be * SRS + ga], Sik_cb = LS[7][ga * SRS + be];
+                const double Sij_bc = LS[12][be * SRS + ga], Sij_cb = LS[13][ga * SRS + be];
+                for (int al = 0; al < SB; ++al) {
+                    const int a = SB * x + al;
+                    if (a > b) break;
+                    if (a == c) continue;  // a = b = c
+                    const double w0 = (double)L[0][al * PS + be * RS + ga];
+                    const double w1 = (double)L[1][al * PS + ga * RS + be];
+                    const double w2 = (double)L[2][be * PS + al * RS + ga];
+                    const double w3 = (double)L[3][be * PS + ga * RS + al];
+                    const double w4 = (double)L[4][ga * PS + al * RS + be];
+                    const double w5 = (double)L[5][ga * PS + be * RS + al];
+                    const double t1ia = LT[0][0][al], t1ja = LT[1][0][al], t1ka = LT[2][0][al];
+                    // pairs: Q2 (x,z) [al][ga], Q3 (z,x) [ga][al], Q4 (x,y) [al][be], Q5 (y,x) [be][al]
+                    const double Sjk_ac = LS[2][al * SRS + ga], Sjk_ca = LS[3][ga * SRS + al];
+                    const double Sjk_ab = LS[4][al * SRS + be], Sjk_ba = LS[5][be * SRS + al];
+                    const double Sik_ac = LS[8][al * SRS + ga], Sik_ca = LS[9][ga * SRS + al];
+                    const double Sik_ab = LS[10][al * SRS + be], Sik_ba = LS[11][be * SRS + al];
+                    const double Sij_ac = LS[14][al * SRS + ga], Sij_ca = LS[15][ga * SRS + al];
+                    const double Sij_ab = LS[16][al * SRS + be], Sij_ba = LS[17][be * SRS + al];
+                    // Z(x,y,z) = t1[i][x] (jy|kz) + t1[j][y] (ix|kz) + t1[k][z] (ix|jy)
+                    const double z0 = t1ia * Sjk_bc + t1jb * Sik_ac + t1kc * Sij_ab;   // (a,b,c)
+                    const double z1 = t1ia * Sjk_cb + t1jc * Sik_ab + t1kb * Sij_ac;   // (a,c,b)
+                    const double z2 = t1ib * Sjk_ac + t1ja * Sik_bc + t1kc * Sij_ba;   // (b,a,c)
+                    const double z3 = t1ib * Sjk_ca + t1jc * Sik_ba + t1ka * Sij_bc;   // (b,c,a)
+                    const double z4 = t1ic * Sjk_ab + t1ja * Sik_cb + t1kb * Sij_ca;   // (c,a,b)
+                    const double z5 = t1ic * Sjk_ba + t1jb * Sik_ca + t1ka * Sij_cb;   // (c,b,a)
+                    const double We = w0 + w3 + w4, Wo = w1 + w2 + w5;
+                    const double Ze = z0 + z3 + z4, Zo = z1 + z2 + z5;
+                    const double sww = w0 * w0 + w1 * w1 + w2 * w2 + w3 * w3 + w4 * w4 + w5 * w5;
+                    const double swz = w0 * z0 + w1 * z1 + w2 * z2 + w3 * z3 + w4 * z4 + w5 * z5;
+                    const double f4 = 3.0 * sww + We * (We - 2.0 * Wo) + Wo * (Wo - 2.0 * We);
+                    const double f5 = 3.0 * swz + We * (Ze - 2.0 * Zo) + Wo * (Zo - 2.0 * Ze);
+                    const double D = eo - LT[3][0][al] - evbc;
+                    const double rep = (a == b || b == c) ? 2.0 : 1.0;
+                    const double sc = scale / (rep * D);
+                    e4 += f4 * sc;
+                    e5 += f5 * sc;
+                }
+            }
+        }
+        __syncthreads();
     }
     const double s4 = block_sum(e4, sh);
     const double s5 = block_sum(e5, sh);
@@ -129,7 +252,7 @@ __global__ __launch_bounds__(256) void slot_reduce_kernel(const Slot* __restrict
                                                           double* __restrict__ e_trip) {
     __shared__ double sh[4];
     const Slot* S = slots + blockIdx.x;
-    const int nb = S->nblk;
+    const int nb = S->nbw;
     const int norb = nb * (nb + 1) * (nb + 2) / 6;
     double e4 = 0.0, e5 = 0.0;
     for (int q = threadIdx.x; q < norb; q += 256) {
@@ -166,17 +289,22 @@ __global__ __launch_bounds__(256) void final_reduce_kernel(const int* __restrict
 }
 
 template <class WT>
-__global__ void widen_kernel(const WT* __restrict__ w, int64_t n, double* __restrict__ out) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        out[e] = (double)w[e];
+__global__ void widen_kernel(const WT* __restrict__ w, int v, double* __restrict__ out) {
+    const int nb = (v + WB - 1) / WB;
+    const int64_t n = (int64_t)v * v * v;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e % v), b = (int)((e / v) % v), a = (int)(e / ((int64_t)v * v));
+        const int64_t half = (int64_t)nb * nb * nb * (WB * WB * WB);
+        out[e] = (double)(WT)(w[w_index(a, b, c, nb)] + w[half + w_index(a, b, c, nb)]);
+    }
 }
 
 hipError_t launch_energy(int prec, const Slot* d_slots, int nslot, int total, double* partials, hipStream_t s) {
     if (total <= 0) return hipSuccess;
     if (prec == P_FP64)
-        hipLaunchKernelGGL(energy_kernel<double>, dim3(total), dim3(256), 0, s, d_slots, nslot, partials);
+        hipLaunchKernelGGL(energy_kernel<double>, dim3(total), dim3(EW * 64), 0, s, d_slots, nslot, partials);
     else
-        hipLaunchKernelGGL(energy_kernel<float>, dim3(total), dim3(256), 0, s, d_slots, nslot, partials);
+        hipLaunchKernelGGL(energy_kernel<float>, dim3(total), dim3(EW * 64), 0, s, d_slots, nslot, partials);
     return hipGetLastError();
 }
 
@@ -193,12 +321,13 @@ hipError_t launch_final_reduce(const int* d_trip_begin, int nprob, const double*
     return hipGetLastError();
 }
 
-hipError_t launch_widen_w(int prec, const void* w, int64_t n, double* out, hipStream_t s) {
+hipError_t launch_widen_w(int prec, const void* w, int v, double* out, hipStream_t s) {
+    const int64_t n = (int64_t)v * v * v;
     const int grid = (int)std::min<int64_t>((n + 255) / 256, 65536);
     if (prec == P_FP64)
-        hipLaunchKernelGGL(widen_kernel<double>, dim3(grid), dim3(256), 0, s, static_cast<const double*>(w), n, out);
+        hipLaunchKernelGGL(widen_kernel<double>, dim3(grid), dim3(256), 0, s, static_cast<const double*>(w), v, out);
     else
-        hipLaunchKernelGGL(widen_kernel<float>, dim3(grid), dim3(256), 0, s, static_cast<const float*>(w), n, out);
+        hipLaunchKernelGGL(widen_kernel<float>, dim3(grid), dim3(256), 0, s, static_cast<const float*>(w), v, out);
     return hipGetLastError();
 }
 

@@ -160,6 +160,29 @@ def test_odd_shapes_mixed(ctx, o, v, prec):
     assert np.all(np.abs(Wm - ref_w) <= w_bound(p, t, prec))
 
 
+# ------------------------------------------------------------- tile configs
+@pytest.fixture(scope="module")
+def tile_cases():
+    cases = []
+    for (o, v) in [(3, 45), (4, 130)]:
+        p = synth.make_problem(o, v, seed=700 + v)
+        cases.append((p, oracle.triples_energy(*_args(p))))
+    return cases
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_every_tile_config(ctx, tile_cases, cfg, prec, monkeypatch):
+    monkeypatch.setenv("CCSDT_TILE", str(cfg))
+    for p, ref in tile_cases:
+        say(f"tile cfg={cfg} {prec} o={p['nocc']} v={p['nvirt']}")
+        E, E4, E5 = ctx.energy(synth.to_device(p), prec)
+        if prec == "fp64":
+            assert abs(E - ref[0]) <= 1e-10 * abs(ref[1])
+        else:
+            assert abs(E - ref[0]) <= max(mixed_tol(ref[0]), 2 * U_TERM[prec] * 1e-2 * abs(ref[1]))
+
+
 # ------------------------------------------------------------------- invariants
 def test_relabeling_invariance_gpu(ctx):
     from tests.test_oracle_pins import relabel
