@@ -79,10 +79,12 @@ __host__ __device__ inline int64_t w_index(int a, int b, int c, int nb) {
 // plane of one batch index).  0-2: operands loaded straight from global
 // memory into MFMA fragments, 2x2 waves.  3-5: operands staged through
 // double-buffered LDS, 2x2 waves.
+// 6-7: as 3-4 with operands written straight from global memory into LDS
+// (global_load_lds), without a register round trip.
 struct TileCfg { int bm, bn, lds; };
-constexpr int NTILE_CFG = 6;
+constexpr int NTILE_CFG = 8;
 constexpr TileCfg TILE_CFGS[NTILE_CFG] = {
-    {64, 64, 0}, {128, 64, 0}, {128, 128, 0}, {128, 128, 1}, {128, 256, 1}, {64, 128, 1}};
+    {64, 64, 0}, {128, 64, 0}, {128, 128, 0}, {128, 128, 1}, {128, 256, 1}, {64, 128, 1}, {128, 128, 2}, {128, 256, 2}};
 inline int tile_m(int cfg) { return TILE_CFGS[cfg].bm; }
 inline int tile_n(int cfg) { return TILE_CFGS[cfg].bn; }
 

@@ -52,11 +52,13 @@ struct PrecF64 {
     static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
         f.x = *reinterpret_cast<const GLOBAL f64x4*>(gp(row + c * 16 + 4 * (lane >> 4)));
     }
-    // LDS staging: one k sub-step spans SUB_BYTES of a row; lane group l/16
-    // reads LANE_BYTES of it.
-    static constexpr int SUB_BYTES = 128, LANE_BYTES = 32;
-    static __device__ __forceinline__ void load_lds(Frag& f, const char* p) {
-        f.x = *reinterpret_cast<const f64x4*>(p);
+    // LDS staging (128-byte rows of eight 16-byte chunks, see contract_lds_kernel).
+    static constexpr int NSUB = 1;     // k sub-steps per 128-byte LDS row chunk set
+    static constexpr bool SPLIT = true;  // a lane's 32 bytes live in LDS chunks g and 4 + g
+    static __device__ __forceinline__ void load_lds(Frag& f, const char* row, int g, int sub, int sw) {
+        const double2 x0 = *reinterpret_cast<const double2*>(row + 16 * (g ^ sw));
+        const double2 x1 = *reinterpret_cast<const double2*>(row + 16 * ((4 + g) ^ sw));
+        f.x = f64x4{x0.x, x0.y, x1.x, x1.y};
     }
     static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[0], b.x[0], acc, 0, 0, 0);
@@ -77,9 +79,10 @@ struct PrecF32 {
     static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
         f.x = *reinterpret_cast<const GLOBAL f32x4*>(gp(row + c * 16 + 4 * (lane >> 4)));
     }
-    static constexpr int SUB_BYTES = 64, LANE_BYTES = 16;
-    static __device__ __forceinline__ void load_lds(Frag& f, const char* p) {
-        f.x = *reinterpret_cast<const f32x4*>(p);
+    static constexpr int NSUB = 2;
+    static constexpr bool SPLIT = false;  // sub-step s, lane group g reads LDS chunk 4 s + g
+    static __device__ __forceinline__ void load_lds(Frag& f, const char* row, int g, int sub, int sw) {
+        f.x = *reinterpret_cast<const f32x4*>(row + 16 * ((4 * sub + g) ^ sw));
     }
     static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[0], b.x[0], acc, 0, 0, 0);
@@ -102,10 +105,11 @@ struct PrecB3 {
         f.hi = *reinterpret_cast<const GLOBAL bf16x8*>(p);
         f.lo = *reinterpret_cast<const GLOBAL bf16x8*>(p + 8);
     }
-    static constexpr int SUB_BYTES = 128, LANE_BYTES = 32;
-    static __device__ __forceinline__ void load_lds(Frag& f, const char* p) {
-        f.hi = *reinterpret_cast<const bf16x8*>(p);
-        f.lo = *reinterpret_cast<const bf16x8*>(p + 16);
+    static constexpr int NSUB = 1;
+    static constexpr bool SPLIT = true;  // hi of group g in LDS chunk g, lo in chunk 4 + g
+    static __device__ __forceinline__ void load_lds(Frag& f, const char* row, int g, int sub, int sw) {
+        f.hi = *reinterpret_cast<const bf16x8*>(row + 16 * (g ^ sw));
+        f.lo = *reinterpret_cast<const bf16x8*>(row + 16 * ((4 + g) ^ sw));
     }
     static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
@@ -264,16 +268,16 @@ __global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ 
 
 // MFMAs over one LDS stage for a wave's MB x NB blocks.  FULL skips the
 // per-block edge tests (interior tiles), keeping the MFMA stream branch-free.
-template <class P, int MB, int NB, int NSUB, int RS, bool FULL>
-__device__ __forceinline__ void lds_stage(typename P::Acc (&acc)[MB][NB], const char* As, const char* Bs, int vm,
-                                          int vn) {
+template <class P, int MB, int NB, int RS, bool FULL>
+__device__ __forceinline__ void lds_stage(typename P::Acc (&acc)[MB][NB], const char* As, const char* Bs, int g,
+                                          int sw, int vm, int vn) {
 #pragma unroll
-    for (int sub = 0; sub < NSUB; ++sub) {
+    for (int sub = 0; sub < P::NSUB; ++sub) {
         typename P::Frag fa[MB], fb[NB];
 #pragma unroll
-        for (int a = 0; a < MB; ++a) P::load_lds(fa[a], As + a * 16 * RS + sub * P::SUB_BYTES);
+        for (int a = 0; a < MB; ++a) P::load_lds(fa[a], As + a * 16 * RS, g, sub, sw);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) P::load_lds(fb[b], Bs + b * 16 * RS + sub * P::SUB_BYTES);
+        for (int b = 0; b < NB; ++b) P::load_lds(fb[b], Bs + b * 16 * RS, g, sub, sw);
 #pragma unroll
         for (int a = 0; a < MB; ++a)
 #pragma unroll
@@ -284,23 +288,32 @@ __device__ __forceinline__ void lds_stage(typename P::Acc (&acc)[MB][NB], const 
 
 // LDS-staged variant.  Each workgroup (2x2 waves, wave tile WTM x WTN)
 // streams its BM + BN operand rows through two LDS stages of ROWB bytes per
-// row (padded by 16 bytes so that the 16 lanes of one fragment read hit
-// distinct banks), one barrier per stage; the next stage is fetched into
-// registers while the current one feeds the MFMAs.
-template <class P, int WTM, int WTN, int ROWB, int MINB>
+// row, one barrier per stage; the next stage is fetched into registers while
+// the current one feeds the MFMAs.  A stage row holds 128 bytes of one
+// operand row as eight 16-byte chunks.  For BF16X3 (hi/lo of k-group g) and
+// FP64 (two halves of lane group g's 32 bytes) the first half goes to chunk
+// g and the second to chunk 4 + g; FP32 keeps the global order (sub-step s,
+// group g at chunk 4 s + g).  The chunk index is then XOR-ed with
+// lds_swz(row).  With this layout, measured with the LDS bank-conflict
+// counter over all XOR swizzles of this family, the fragment reads (16 rows
+// x 4 lane groups) and the staging writes (8 rows x 8 chunks per wave) are
+// free of bank conflicts.
+__device__ __forceinline__ int lds_swz(int row) { return (((row >> 1) & 1) << 2) | (((row >> 2) & 1) << 1); }
+
+template <class P, int WTM, int WTN, int ROWB, int MINB, bool DIRECT>
 __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __restrict__ slots, int nslot,
                                                                   int total) {
     using E = typename P::E;
     constexpr int NT = 256;
     constexpr int BM = 2 * WTM, BN = 2 * WTN;
-    constexpr int RS = ROWB + 16;
+    constexpr int RS = ROWB;
     constexpr int ROWS = BM + BN;
     constexpr int TPR = ROWB / 16;
     constexpr int RPP = NT / TPR;
     constexpr int NP = ROWS / RPP;
     static_assert(ROWS % RPP == 0, "rows must split evenly over the threads");
     constexpr int MB = WTM / 16, NB = WTN / 16;
-    constexpr int NSUB = ROWB / P::SUB_BYTES;
+    static_assert(ROWB == 128, "stage rows are eight 16-byte chunks");
     __shared__ __attribute__((aligned(16))) char lds[2 * ROWS * RS];
 
     const int bid = xcd_remap(blockIdx.x, total);
@@ -320,6 +333,17 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
     const char* G = static_cast<const char*>(S->gc);
     const char* T = static_cast<const char*>(S->tc);
     const int lrow = threadIdx.x / TPR, lcol = (threadIdx.x % TPR) * 16;
+    // LDS chunk of this thread's staging chunk (RPP keeps the swizzle bits)
+    static_assert(RPP % 8 == 0, "staging rows must keep the swizzle bits");
+    const int gch = lcol >> 4;
+    const int lch = P::SPLIT ? ((gch & 1) * 4 + (gch >> 1)) : gch;
+    const int lcol_sw = (lch ^ lds_swz(lrow)) * 16;
+    // Direct staging (global_load_lds): lane l of a wave's p-th load writes the
+    // 16 bytes at LDS row lrow + p RPP, chunk l % 8; it fetches the global chunk
+    // that belongs there under the same permutation and swizzle.
+    const int pch = (lane & 7) ^ lds_swz(lrow);
+    const int src_col = (P::SPLIT ? (((pch & 3) << 1) | (pch >> 2)) : pch) * 16;
+    const int wave_row0 = (threadIdx.x >> 6) * (64 / TPR);
 
     // Byte offset of each of this thread's rows for the current segment,
     // relative to the segment's A or B operand array.
@@ -334,16 +358,17 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
 #define CCSDT_SET_PTRS(sg)                                                          \
     {                                                                               \
         const SegRows g_ = segment(pass, (sg), S->i, S->j, S->k, o, v);             \
+        const int col_ = DIRECT ? src_col : lcol;                                   \
         baseA = g_.aG ? G : T;                                                      \
         baseB = g_.bG ? G : T;                                                      \
         _Pragma("unroll") for (int p = 0; p < NP; ++p) {                            \
             const int r = lrow + p * RPP;                                           \
             if (r < BM) {                                                           \
                 const int m = min(mt0 + r, v - 1);                                  \
-                roff[p] = (g_.a0 + beta * g_.aB + m * g_.aM) * rowbytes + lcol;     \
+                roff[p] = (g_.a0 + beta * g_.aB + m * g_.aM) * rowbytes + col_;     \
             } else {                                                                \
                 const int n = min(nt0 + r - BM, v - 1);                             \
-                roff[p] = (g_.b0 + beta * g_.bB + n * g_.bN) * rowbytes + lcol;     \
+                roff[p] = (g_.b0 + beta * g_.bB + n * g_.bN) * rowbytes + col_;     \
             }                                                                       \
         }                                                                           \
     }
@@ -352,9 +377,16 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
         const char* src = ((lrow + p * RPP) < BM ? baseA : baseB) + roff[p] + (int64_t)(c) * ROWB; \
         st[p] = *reinterpret_cast<const GLOBAL u32x4*>(gp(src));                               \
     }
+#define CCSDT_GLOAD_DIRECT(c, buf)                                                             \
+    _Pragma("unroll") for (int p = 0; p < NP; ++p) {                                           \
+        const char* src = ((lrow + p * RPP) < BM ? baseA : baseB) + roff[p] + (int64_t)(c) * ROWB; \
+        char* dst = lds + (buf) * (ROWS * RS) + (wave_row0 + p * RPP) * RS;                    \
+        __builtin_amdgcn_global_load_lds((const GLOBAL void*)gp(src),                          \
+                                         (__attribute__((address_space(3))) void*)dst, 16, 0, 0); \
+    }
 #define CCSDT_LSTORE(buf)                                                                      \
     {                                                                                          \
-        char* dst_ = lds + (buf) * (ROWS * RS) + lrow * RS + lcol;                             \
+        char* dst_ = lds + (buf) * (ROWS * RS) + lrow * RS + lcol_sw;                          \
         _Pragma("unroll") for (int p = 0; p < NP; ++p)                                         \
             *reinterpret_cast<u32x4*>(dst_ + p * RPP * RS) = st[p];                            \
     }
@@ -362,35 +394,48 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
     const char* baseA = G;
     const char* baseB = T;
     CCSDT_SET_PTRS(0);
-    CCSDT_GLOAD(0);
-    CCSDT_LSTORE(0);
+    if constexpr (DIRECT) {
+        CCSDT_GLOAD_DIRECT(0, 0);
+    } else {
+        CCSDT_GLOAD(0);
+        CCSDT_LSTORE(0);
+    }
     __syncthreads();
     const bool active = vm > 0 && vn > 0;
     int sg_next = 0, c_next = 0;
     for (int step = 0; step < nsteps; ++step) {
         const int buf = step & 1;
-        const bool more = step + 1 < nsteps;
-        if (more) {
-            if (++c_next == csteps) {
-                c_next = 0;
-                ++sg_next;
-                CCSDT_SET_PTRS(sg_next);
-            }
+        // Prefetch the next stage (the last step re-reads its own chunk, so the
+        // loads and the LDS store below are unconditional: a branch around them
+        // lets the compiler sink the loads past the MFMAs and expose their
+        // latency on every stage).
+        if (step + 1 < nsteps && ++c_next == csteps) {
+            c_next = 0;
+            ++sg_next;
+            CCSDT_SET_PTRS(sg_next);
+        }
+        if constexpr (DIRECT) {
+            CCSDT_GLOAD_DIRECT(c_next, buf ^ 1);
+        } else {
             CCSDT_GLOAD(c_next);
         }
+        __builtin_amdgcn_sched_barrier(0);
         if (active) {
-            const char* As = lds + buf * (ROWS * RS) + (wm * WTM + (lane & 15)) * RS + (lane >> 4) * P::LANE_BYTES;
-            const char* Bs = lds + buf * (ROWS * RS) + (BM + wn * WTN + (lane & 15)) * RS + (lane >> 4) * P::LANE_BYTES;
+            const char* As = lds + buf * (ROWS * RS) + (wm * WTM + (lane & 15)) * RS;
+            const char* Bs = lds + buf * (ROWS * RS) + (BM + wn * WTN + (lane & 15)) * RS;
+            const int g = lane >> 4;
+            const int sw = lds_swz(lane & 15);
             if (vm == MB && vn == NB)
-                lds_stage<P, MB, NB, NSUB, RS, true>(acc, As, Bs, vm, vn);
+                lds_stage<P, MB, NB, RS, true>(acc, As, Bs, g, sw, vm, vn);
             else
-                lds_stage<P, MB, NB, NSUB, RS, false>(acc, As, Bs, vm, vn);
+                lds_stage<P, MB, NB, RS, false>(acc, As, Bs, g, sw, vm, vn);
         }
-        if (more) CCSDT_LSTORE(buf ^ 1);
+        if constexpr (!DIRECT) CCSDT_LSTORE(buf ^ 1);
         __syncthreads();
     }
 #undef CCSDT_SET_PTRS
 #undef CCSDT_GLOAD
+#undef CCSDT_GLOAD_DIRECT
 #undef CCSDT_LSTORE
     if (active) store_tile<P, MB, NB>(S, pass, beta, m0, n0, vm, vn, lane, acc);
 }
@@ -401,9 +446,11 @@ static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int tot
         case 0: hipLaunchKernelGGL((contract_kernel<P, 2, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 1: hipLaunchKernelGGL((contract_kernel<P, 4, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 2: hipLaunchKernelGGL((contract_kernel<P, 4, 4>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
-        case 3: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 64, 128, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
-        case 4: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 128, 128, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
-        case 5: hipLaunchKernelGGL((contract_lds_kernel<P, 32, 64, 128, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 3: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 64, 128, 2, false>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 4: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 128, 128, 1, false>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 5: hipLaunchKernelGGL((contract_lds_kernel<P, 32, 64, 128, 2, false>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 6: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 64, 128, 2, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 7: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 128, 128, 1, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
