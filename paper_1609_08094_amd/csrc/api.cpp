@@ -55,9 +55,21 @@ int env_int(const char* name, int dflt) {
 
 }  // namespace
 
+struct GraphEntry {
+    bool valid = false;
+    int prec = -1;
+    uint64_t gen = 0;
+    std::vector<ccsdt_problem> probs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* host = nullptr;      // pinned copies of the slot table, triple ranges and problem table
+    size_t host_bytes = 0;
+};
+
 struct ccsdt_context {
     int device = 0;
-    DevBuf gc, tc, w, part, etrip, slots, out, tripbeg;
+    DevBuf gc, tc, w, part, etrip, slots, out, tripbeg, pdesc;
+    uint64_t gen = 0;          // bumped whenever a device buffer is (re)allocated
     size_t cap = 0;            // CCSDT_MAX_DEVICE_BYTES (0 = none)
     size_t w_budget = 0;       // bytes of W per chunk
     double* host_out = nullptr;
@@ -72,9 +84,13 @@ struct ccsdt_context {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<int> ev_class;
+    std::map<std::pair<int, int>, int> plans;  // (precision, v bucket) -> tile configuration
+    int forced_cfg = -1;                       // set by the autotuner while it measures
+    GraphEntry graph;
 
     size_t allocated() const {
-        return gc.bytes + tc.bytes + w.bytes + part.bytes + etrip.bytes + slots.bytes + out.bytes + tripbeg.bytes;
+        return gc.bytes + tc.bytes + w.bytes + part.bytes + etrip.bytes + slots.bytes + out.bytes + tripbeg.bytes +
+               pdesc.bytes;
     }
 };
 
@@ -100,6 +116,7 @@ int ensure(ccsdt_context* ctx, DevBuf& b, size_t bytes, const char* what) {
     }
     b.p = p;
     b.bytes = bytes;
+    ++ctx->gen;
     return CCSDT_OK;
 }
 
@@ -244,7 +261,7 @@ int tile_cfg_for(int prec, int v) {
     int forced = env_int("CCSDT_TILE", -1);
     if (forced >= 0 && forced < NTILE_CFG) return forced;
     (void)prec;
-    return v >= 64 ? 3 : 0;
+    return v >= 64 ? 6 : 0;
 }
 
 struct ProbLayout {
