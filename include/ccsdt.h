@@ -133,11 +133,45 @@ int ccsdt_debug_w(ccsdt_context* ctx, const ccsdt_problem* prob, int precision,
                   int i, int j, int k, void* hip_stream, double* w_host);
 
 /* Many independent problems of uneven (nocc, nvirt) in one submission: the
- * triples of all problems form one work list processed by one captured HIP
- * graph (Sec. 3: loop cycles are data independent).  out_host[3*p+0..2] =
- * (E, E4, E5) of problem p. */
+ * triples of all problems form one work list (Sec. 3: the cycles of the
+ * collapsed loop are independent), grouped by tile plan, and each
+ * contraction launch takes triples of several problems at once.  The
+ * submission runs as one captured HIP graph (see ccsdt_graph_stats).
+ * out_host[3*p+0..2] = (E, E4, E5) of problem p.  A problem whose orbital
+ * energies are not finite gives CCSDT_EINVAL, one with max(eps_o) >=
+ * min(eps_v) CCSDT_EDENOM; both name the problem in ccsdt_last_error(). */
 int ccsdt_energy_batched(ccsdt_context* ctx, int nprob, const ccsdt_problem* probs_host,
                          int precision, void* hip_stream, double* out_host);
+
+/* Tile plans.  The contraction kernel has NTILE = 12 tile configurations
+ * (workgroup tile shape, operand staging through registers or LDS, direct
+ * global-to-LDS loads, one or two batch indices per workgroup, fragment
+ * prefetch), numbered 0..11.  The context keeps one choice per (precision, nvirt
+ * bucket), a bucket spanning nvirt in (2^(b-1), 2^b]; unset buckets use the
+ * built-in default.  The environment variable CCSDT_TILE=<cfg> overrides
+ * every plan (testing aid).
+ *
+ * ccsdt_autotune times the contraction of every configuration on up to four
+ * triples of ``prob`` (each twice, the second run counted) and stores the
+ * fastest as the plan of prob's bucket; *cfg_out (may be NULL) receives it.
+ * The timing launches do not count in the profile.  ccsdt_plan_get returns
+ * the configuration a call with this nvirt would use; ccsdt_plan_set stores
+ * one (cfg = -1 clears the bucket).  Changing a plan invalidates captured
+ * graphs. */
+int ccsdt_autotune(ccsdt_context* ctx, const ccsdt_problem* prob, int precision,
+                   void* hip_stream, int* cfg_out);
+int ccsdt_plan_get(ccsdt_context* ctx, int precision, int nvirt, int* cfg_out);
+int ccsdt_plan_set(ccsdt_context* ctx, int precision, int nvirt, int cfg);
+
+/* Graph reuse of ccsdt_energy_batched: with nprob > 1 and profiling off, the
+ * whole submission (denominator check, packs, contractions, energies,
+ * reductions and the result copy) is captured once into a HIP graph and
+ * replayed while the problem list (sizes and pointers), the precision, the
+ * plans and the context's workspace buffers stay the same.  A replay reads
+ * the current contents of the inputs.  CCSDT_GRAPH=0 in the environment
+ * disables capture.  ccsdt_graph_stats returns the number of captures and
+ * replays since the context was created. */
+int ccsdt_graph_stats(ccsdt_context* ctx, int64_t* captures, int64_t* replays);
 
 /* Kernel timing: when enabled, every launch of each kernel class is bracketed
  * by HIP events on the launch stream, and ccsdt_profile_get returns the

@@ -21,7 +21,9 @@ KERNEL_CLASSES = {"pack": 0, "contract": 1, "energy": 2, "reduce": 3}
 FIELDS = ("eps_o", "eps_v", "t1", "t2", "vvvo", "ovoo", "ovov")
 EXPORTS = ("ccsdt_context_create", "ccsdt_context_destroy", "ccsdt_energy", "ccsdt_triples_energy",
            "ccsdt_triple_energies", "ccsdt_debug_w", "ccsdt_energy_batched", "ccsdt_profile_enable",
-           "ccsdt_profile_get", "ccsdt_profile_reset", "ccsdt_flops", "ccsdt_last_error")
+           "ccsdt_profile_get", "ccsdt_profile_reset", "ccsdt_flops", "ccsdt_last_error", "ccsdt_autotune",
+           "ccsdt_plan_get", "ccsdt_plan_set", "ccsdt_graph_stats")
+NTILE_CFG = 12
 
 
 class CcsdtError(RuntimeError):
@@ -58,6 +60,10 @@ def load_library(path: str = LIB_PATH):
     lib.ccsdt_profile_enable.argtypes = [vp, ip]
     lib.ccsdt_profile_get.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int64), dp]
     lib.ccsdt_profile_reset.argtypes = [vp]
+    lib.ccsdt_autotune.argtypes = [vp, P, ip, vp, ctypes.POINTER(ip)]
+    lib.ccsdt_plan_get.argtypes = [vp, ip, ip, ctypes.POINTER(ip)]
+    lib.ccsdt_plan_set.argtypes = [vp, ip, ip, ip]
+    lib.ccsdt_graph_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.ccsdt_flops.argtypes = [ip, ip]
     lib.ccsdt_flops.restype = ctypes.c_double
     lib.ccsdt_last_error.restype = ctypes.c_char_p
@@ -161,6 +167,28 @@ class Context:
         _check(load_library().ccsdt_debug_w(self._h, ctypes.byref(p), _prec(precision), i, j, k,
                                              _stream(stream), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return w
+
+    # -- plans and graphs ------------------------------------------------------
+    def autotune(self, prob: dict, precision="fp64", stream=None) -> int:
+        """Time every tile configuration on a few triples; keep the fastest."""
+        p = make_problem_struct(prob)
+        cfg = ctypes.c_int()
+        _check(load_library().ccsdt_autotune(self._h, ctypes.byref(p), _prec(precision), _stream(stream),
+                                              ctypes.byref(cfg)))
+        return cfg.value
+
+    def plan_get(self, precision, nvirt: int) -> int:
+        cfg = ctypes.c_int()
+        _check(load_library().ccsdt_plan_get(self._h, _prec(precision), int(nvirt), ctypes.byref(cfg)))
+        return cfg.value
+
+    def plan_set(self, precision, nvirt: int, cfg: int):
+        _check(load_library().ccsdt_plan_set(self._h, _prec(precision), int(nvirt), int(cfg)))
+
+    def graph_stats(self) -> tuple[int, int]:
+        c, r = ctypes.c_int64(), ctypes.c_int64()
+        _check(load_library().ccsdt_graph_stats(self._h, ctypes.byref(c), ctypes.byref(r)))
+        return c.value, r.value
 
     # -- profiling ----------------------------------------------------------
     def profile(self, on: bool = True):

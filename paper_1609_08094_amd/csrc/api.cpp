@@ -62,8 +62,9 @@ struct GraphEntry {
     std::vector<ccsdt_problem> probs;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    void* host = nullptr;      // pinned copies of the slot table, triple ranges and problem table
+    void* host = nullptr;      // pinned: slot table, triple ranges, problem table, results
     size_t host_bytes = 0;
+    size_t layout_out = 0;     // byte offset of the result rows in ``host``
 };
 
 struct ccsdt_context {
@@ -87,6 +88,8 @@ struct ccsdt_context {
     std::map<std::pair<int, int>, int> plans;  // (precision, v bucket) -> tile configuration
     int forced_cfg = -1;                       // set by the autotuner while it measures
     GraphEntry graph;
+    hipStream_t cap_stream = nullptr;          // private stream used only for graph capture
+    int64_t n_captures = 0, n_replays = 0;
 
     size_t allocated() const {
         return gc.bytes + tc.bytes + w.bytes + part.bytes + etrip.bytes + slots.bytes + out.bytes + tripbeg.bytes +
@@ -257,10 +260,21 @@ size_t elem_bytes(int prec) { return prec == CCSDT_FP64 ? 8 : 4; }   // packed e
 size_t w_bytes(int prec) { return prec == CCSDT_FP64 ? 8 : 4; }
 
 // ---- plans ---------------------------------------------------------------------
-int tile_cfg_for(int prec, int v) {
+// Tile plans are kept per (precision, v bucket); a bucket spans v in
+// (2^(b-1), 2^b].  Without an autotuned entry the direct-to-LDS 128x128 tile
+// is used for v >= 64 and the register-direct 64x64 tile below.
+int v_bucket(int v) {
+    int b = 0;
+    while ((1 << b) < v) ++b;
+    return b;
+}
+
+int tile_cfg_for(const ccsdt_context* ctx, int prec, int v) {
+    if (ctx->forced_cfg >= 0) return ctx->forced_cfg;
     int forced = env_int("CCSDT_TILE", -1);
     if (forced >= 0 && forced < NTILE_CFG) return forced;
-    (void)prec;
+    auto it = ctx->plans.find({prec, v_bucket(v)});
+    if (it != ctx->plans.end()) return it->second;
     return v >= 64 ? 6 : 0;
 }
 
@@ -275,24 +289,38 @@ struct TripRef {
     int prob, i, j, k, mult, out_index;
 };
 
+struct Chunk {
+    size_t first, n;  // slots [first, first + n)
+    int totA, totE;   // contraction / energy workgroups
+    int cfg;          // tile configuration (uniform inside a chunk)
+};
+
+// Everything a pipeline run needs besides the stream: problem layouts, the
+// work list, its chunks and the slot table (host copy).
+struct Plan {
+    std::vector<ProbLayout> probs;
+    std::vector<TripRef> trips;
+    std::vector<Chunk> chunks;
+    std::vector<Slot> slots;
+    size_t n_out = 0;     // rows of the per-triple energy buffer
+    bool one_per_chunk = false;
+};
+
 int multiplicity(int i, int j, int k) {
     if (i == j && j == k) return 0;
     if (i == j || j == k || i == k) return 3;
     return 6;
 }
 
-// Packs every problem, then runs the chunked pipeline over ``trips``, leaving
-// (e, e4, e5) of trip t in e_trip[3*trips[t].out_index].  If debug_w is set,
-// the W of the single triple is widened into it (v^3 doubles, device).
-int run_pipeline(ccsdt_context* ctx, std::vector<ProbLayout>& probs, const std::vector<TripRef>& trips, int prec,
-                 hipStream_t s, size_t n_out, double* debug_w) {
-    // pack buffers
+// Host phase: tile choice, pooled pack offsets, chunking by the W budget,
+// workspace allocation and the slot table.  Launches nothing.
+int plan_pipeline(ccsdt_context* ctx, Plan& P, int prec) {
     size_t gc_total = 0, tc_total = 0;
     const size_t es = elem_bytes(prec);
-    for (auto& L : probs) {
+    for (auto& L : P.probs) {
         const int64_t o = L.p.nocc, v = L.p.nvirt;
         L.Kp = round_up((int)(o + v), KPAD);
-        L.cfg = tile_cfg_for(prec, (int)v);
+        L.cfg = tile_cfg_for(ctx, prec, (int)v);
         L.gc_off = gc_total;
         L.tc_off = tc_total;
         gc_total += (size_t)(o * v * v * L.Kp) * es;
@@ -300,59 +328,54 @@ int run_pipeline(ccsdt_context* ctx, std::vector<ProbLayout>& probs, const std::
         gc_total = (gc_total + 255) / 256 * 256;
         tc_total = (tc_total + 255) / 256 * 256;
     }
+    // triples of one tile configuration next to each other, so that chunks
+    // (which break where the configuration changes) stay few
+    std::stable_sort(P.trips.begin(), P.trips.end(), [&](const TripRef& x, const TripRef& y) {
+        return P.probs[x.prob].cfg < P.probs[y.prob].cfg;
+    });
     CHK(ensure(ctx, ctx->gc, gc_total, "packed G"));
     CHK(ensure(ctx, ctx->tc, tc_total, "packed T"));
-    for (auto& L : probs) {
-        char* g = static_cast<char*>(ctx->gc.p) + L.gc_off;
-        char* t = static_cast<char*>(ctx->tc.p) + L.tc_off;
-        LAUNCH(K_PACK, launch_pack(prec, L.p.nocc, L.p.nvirt, L.Kp, L.p.vvvo, L.p.t2, L.p.ovoo, g, t, s));
-    }
-    CHK(ensure(ctx, ctx->etrip, std::max<size_t>(n_out, 1) * 3 * sizeof(double), "per-triple energies"));
+    CHK(ensure(ctx, ctx->etrip, std::max<size_t>(P.n_out, 1) * 3 * sizeof(double), "per-triple energies"));
 
-    // chunking by W budget
     const size_t wb = w_bytes(prec);
-    std::vector<std::pair<size_t, size_t>> chunks;  // [begin, end) into trips
+    auto w_of = [&](int v) {
+        const size_t nb = (size_t)((v + WB - 1) / WB);
+        return 2 * nb * nb * nb * WB * WB * WB * wb;   // W_A and W_B
+    };
     size_t max_w = 0, max_part = 0;
-    {
-        size_t b = 0;
-        while (b < trips.size()) {
-            size_t e = b, wsum = 0, psum = 0;
-            while (e < trips.size()) {
-                const int64_t v = probs[trips[e].prob].p.nvirt;
-                const int nb = (int)((v + WB - 1) / WB);
-                const size_t wsz = 2 * (size_t)nb * nb * nb * WB * WB * WB * wb;   // W_A and W_B
-                const size_t psz = (size_t)nb * (nb + 1) * (nb + 2) / 6 * 2 * sizeof(double);
-                if (e > b && wsum + wsz > ctx->w_budget) break;
-                if (e > b && probs[trips[e].prob].cfg != probs[trips[b].prob].cfg) break;
-                wsum += wsz;
-                psum += psz;
-                ++e;
-                if (debug_w) break;
-            }
-            chunks.push_back({b, e});
-            max_w = std::max(max_w, wsum);
-            max_part = std::max(max_part, psum);
-            b = e;
+    P.chunks.clear();
+    for (size_t b = 0; b < P.trips.size();) {
+        size_t e = b, wsum = 0, psum = 0;
+        while (e < P.trips.size()) {
+            const ProbLayout& L = P.probs[P.trips[e].prob];
+            const int nb = (L.p.nvirt + WB - 1) / WB;
+            const size_t wsz = w_of(L.p.nvirt);
+            const size_t psz = (size_t)nb * (nb + 1) * (nb + 2) / 6 * 2 * sizeof(double);
+            if (e > b && wsum + wsz > ctx->w_budget) break;
+            if (e > b && L.cfg != P.probs[P.trips[b].prob].cfg) break;
+            wsum += wsz;
+            psum += psz;
+            ++e;
+            if (P.one_per_chunk) break;
         }
+        P.chunks.push_back({b, e - b, 0, 0, P.probs[P.trips[b].prob].cfg});
+        max_w = std::max(max_w, wsum);
+        max_part = std::max(max_part, psum);
+        b = e;
     }
     CHK(ensure(ctx, ctx->w, max_w, "W ring"));
     CHK(ensure(ctx, ctx->part, max_part, "energy partials"));
-    const size_t nslot_total = trips.size();
-    CHK(ensure(ctx, ctx->slots, std::max<size_t>(nslot_total, 1) * sizeof(Slot), "slot table"));
-    CHK(ensure_host((void**)&ctx->host_slots, &ctx->host_slots_bytes, std::max<size_t>(nslot_total, 1) * sizeof(Slot)));
+    CHK(ensure(ctx, ctx->slots, std::max<size_t>(P.trips.size(), 1) * sizeof(Slot), "slot table"));
 
-    // slot descriptors of every chunk, uploaded once
-    struct ChunkInfo { size_t first, n; int totA, totE; int cfgs; };
-    std::vector<ChunkInfo> cinfo;
-    for (auto& ch : chunks) {
-        ChunkInfo ci{ch.first, ch.second - ch.first, 0, 0, -1};
+    P.slots.assign(P.trips.size(), Slot{});
+    for (auto& ch : P.chunks) {
         size_t woff = 0;
         int64_t poff = 0;
-        for (size_t t = ch.first; t < ch.second; ++t) {
-            const TripRef& tr = trips[t];
-            const ProbLayout& L = probs[tr.prob];
+        for (size_t t = ch.first; t < ch.first + ch.n; ++t) {
+            const TripRef& tr = P.trips[t];
+            const ProbLayout& L = P.probs[tr.prob];
             const int v = L.p.nvirt;
-            Slot& S = ctx->host_slots[t];
+            Slot& S = P.slots[t];
             std::memset(&S, 0, sizeof(Slot));
             S.i = tr.i; S.j = tr.j; S.k = tr.k; S.mult = tr.mult;
             S.o = L.p.nocc; S.v = v; S.Kp = L.Kp; S.prob = tr.prob;
@@ -360,39 +383,236 @@ int run_pipeline(ccsdt_context* ctx, std::vector<ProbLayout>& probs, const std::
             S.tiles_n = (v + tile_n(L.cfg) - 1) / tile_n(L.cfg);
             S.nbw = (v + WB - 1) / WB;
             const int norb = S.nbw * (S.nbw + 1) * (S.nbw + 2) / 6;
-            const int per = 2 * v * S.tiles_m * S.tiles_n;   // pass A then pass B
-            S.a_begin = ci.totA; ci.totA += per;
+            S.bgroups = (v + tile_nbat(L.cfg) - 1) / tile_nbat(L.cfg);
+            const int per = 2 * S.bgroups * S.tiles_m * S.tiles_n;   // pass A then pass B
+            S.a_begin = ch.totA; ch.totA += per;
             S.b_begin = S.a_begin;
-            S.e_begin = ci.totE; ci.totE += norb;
+            S.e_begin = ch.totE; ch.totE += norb;
             S.part_begin = poff; poff += norb;
             S.trip_index = tr.out_index;
             S.gc = static_cast<char*>(ctx->gc.p) + L.gc_off;
             S.tc = static_cast<char*>(ctx->tc.p) + L.tc_off;
             S.w = static_cast<char*>(ctx->w.p) + woff;
-            woff += 2 * (size_t)S.nbw * S.nbw * S.nbw * WB * WB * WB * wb;
+            woff += w_of(v);
             S.eps_o = L.p.eps_o; S.eps_v = L.p.eps_v; S.t1 = L.p.t1; S.ovov = L.p.ovov;
-            ci.cfgs = L.cfg;  // uniform inside a chunk (chunks break where it changes)
         }
-        cinfo.push_back(ci);
     }
-    HIPCHK(hipMemcpyAsync(ctx->slots.p, ctx->host_slots, nslot_total * sizeof(Slot), hipMemcpyHostToDevice, s));
+    return CCSDT_OK;
+}
+
+// Device phase: upload of the slot table (from pinned ``host_slots``), the
+// packs and every chunk's launches, all on stream s.  Nothing here allocates
+// or synchronizes, so the phase can be captured into a graph.  With debug_w
+// the (single) triple's W is widened into it instead of the energy.
+int enqueue_pipeline(ccsdt_context* ctx, const Plan& P, int prec, hipStream_t s, const Slot* host_slots,
+                     double* debug_w) {
+    if (!P.slots.empty())
+        HIPCHK(hipMemcpyAsync(ctx->slots.p, host_slots, P.slots.size() * sizeof(Slot), hipMemcpyHostToDevice, s));
+    for (const auto& L : P.probs) {
+        char* g = static_cast<char*>(ctx->gc.p) + L.gc_off;
+        char* t = static_cast<char*>(ctx->tc.p) + L.tc_off;
+        LAUNCH(K_PACK, launch_pack(prec, L.p.nocc, L.p.nvirt, L.Kp, L.p.vvvo, L.p.t2, L.p.ovoo, g, t, s));
+    }
     const Slot* dslots = static_cast<const Slot*>(ctx->slots.p);
     double* part = static_cast<double*>(ctx->part.p);
     double* etrip = static_cast<double*>(ctx->etrip.p);
-    for (auto& ci : cinfo) {
-        const Slot* d = dslots + ci.first;
-        const int n = (int)ci.n;
-        const int cfg = ci.cfgs;
-        LAUNCH(K_CONTRACT, launch_contract(prec, cfg, d, n, ci.totA, s));
+    for (const auto& ch : P.chunks) {
+        const Slot* d = dslots + ch.first;
+        const int n = (int)ch.n;
+        LAUNCH(K_CONTRACT, launch_contract(prec, ch.cfg, d, n, ch.totA, s));
         if (debug_w) {
-            const int v = ctx->host_slots[ci.first].v;
-            LAUNCH(K_REDUCE, launch_widen_w(prec, ctx->host_slots[ci.first].w, v, debug_w, s));
+            const Slot& S = P.slots[ch.first];
+            LAUNCH(K_REDUCE, launch_widen_w(prec, S.w, S.v, debug_w, s));
             continue;
         }
-        LAUNCH(K_ENERGY, launch_energy(prec, d, n, ci.totE, part, s));
+        LAUNCH(K_ENERGY, launch_energy(prec, d, n, ch.totE, part, s));
         LAUNCH(K_REDUCE, launch_slot_reduce(d, n, 0, part, etrip, s));
     }
     return CCSDT_OK;
+}
+
+// Plan + enqueue with the context's own pinned slot buffer (eager calls).
+int run_pipeline(ccsdt_context* ctx, Plan& P, int prec, hipStream_t s, double* debug_w) {
+    CHK(plan_pipeline(ctx, P, prec));
+    const size_t n = std::max<size_t>(P.slots.size(), 1);
+    CHK(ensure_host((void**)&ctx->host_slots, &ctx->host_slots_bytes, n * sizeof(Slot)));
+    // the previous call's upload from this buffer finished before it returned
+    if (!P.slots.empty()) std::memcpy(ctx->host_slots, P.slots.data(), P.slots.size() * sizeof(Slot));
+    return enqueue_pipeline(ctx, P, prec, s, ctx->host_slots, debug_w);
+}
+
+// Work list of whole problems: every triple i<=j<=k with m != 0, problem by
+// problem; trip_begin[p] .. trip_begin[p+1] are problem p's rows.
+void whole_problem_plan(Plan& P, int nprob, const ccsdt_problem* probs, std::vector<int>& trip_begin) {
+    P.probs.assign(nprob, ProbLayout{});
+    P.trips.clear();
+    trip_begin.assign(nprob + 1, 0);
+    for (int p = 0; p < nprob; ++p) {
+        P.probs[p].p = probs[p];
+        const int o = probs[p].nocc;
+        trip_begin[p] = (int)P.trips.size();
+        for (int i = 0; i < o; ++i)
+            for (int j = i; j < o; ++j)
+                for (int k = j; k < o; ++k) {
+                    const int m = multiplicity(i, j, k);
+                    if (m) P.trips.push_back({p, i, j, k, m, (int)P.trips.size()});
+                }
+    }
+    trip_begin[nprob] = (int)P.trips.size();
+    P.n_out = P.trips.size();
+}
+
+// ---- captured graphs (batched submissions) ------------------------------------
+void graph_reset(GraphEntry& G) {
+    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    if (G.graph) (void)hipGraphDestroy(G.graph);
+    G.exec = nullptr;
+    G.graph = nullptr;
+    G.valid = false;
+    G.probs.clear();
+}
+
+bool graph_matches(const ccsdt_context* ctx, int nprob, const ccsdt_problem* probs, int prec) {
+    const GraphEntry& G = ctx->graph;
+    return G.valid && G.prec == prec && G.gen == ctx->gen && (int)G.probs.size() == nprob &&
+           std::memcmp(G.probs.data(), probs, sizeof(ccsdt_problem) * nprob) == 0;
+}
+
+// Pinned host block of a graph: slot table | trip_begin | gap descriptors | out.
+struct GraphHostLayout {
+    size_t slots_off, tb_off, desc_off, out_off, bytes;
+};
+
+GraphHostLayout graph_host_layout(size_t nslot, int nprob) {
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    GraphHostLayout h;
+    h.slots_off = 0;
+    h.tb_off = al(std::max<size_t>(nslot, 1) * sizeof(Slot));
+    h.desc_off = h.tb_off + al(sizeof(int) * (nprob + 1));
+    h.out_off = h.desc_off + al(sizeof(GapDesc) * nprob);
+    h.bytes = h.out_off + al(sizeof(double) * 4 * nprob);
+    return h;
+}
+
+// Device work of one batched submission: gap flags, the pipeline, the final
+// per-problem reduce and the copy of (E, E4, E5, flag) rows to pinned memory.
+int enqueue_batched(ccsdt_context* ctx, const Plan& P, int nprob, int prec, hipStream_t s, char* host,
+                    const GraphHostLayout& h) {
+    double* out = static_cast<double*>(ctx->out.p);
+    HIPCHK(hipMemcpyAsync(ctx->pdesc.p, host + h.desc_off, sizeof(GapDesc) * nprob, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->tripbeg.p, host + h.tb_off, sizeof(int) * (nprob + 1), hipMemcpyHostToDevice, s));
+    LAUNCH(K_REDUCE, launch_gap_check(static_cast<const GapDesc*>(ctx->pdesc.p), nprob, out + 3 * nprob, s));
+    CHK(enqueue_pipeline(ctx, P, prec, s, reinterpret_cast<const Slot*>(host + h.slots_off), nullptr));
+    LAUNCH(K_REDUCE, launch_final_reduce(static_cast<const int*>(ctx->tripbeg.p), nprob,
+                                         static_cast<const double*>(ctx->etrip.p), out, s));
+    HIPCHK(hipMemcpyAsync(host + h.out_off, out, sizeof(double) * 4 * nprob, hipMemcpyDeviceToHost, s));
+    return CCSDT_OK;
+}
+
+int capture_batched(ccsdt_context* ctx, const Plan& P, int nprob, int prec, char* host, const GraphHostLayout& h) {
+    GraphEntry& G = ctx->graph;
+    if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_batched(ctx, P, nprob, prec, ctx->cap_stream, host, h);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (rc != CCSDT_OK || e != hipSuccess) {
+        (void)hipGetLastError();
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc != CCSDT_OK ? rc : fail(CCSDT_EHIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(graph);
+        return fail(CCSDT_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(e));
+    }
+    G.graph = graph;
+    G.exec = exec;
+    return CCSDT_OK;
+}
+
+int check_flags(const double* flags, int nprob) {
+    for (int p = 0; p < nprob; ++p) {
+        const std::string where = nprob > 1 ? " (problem " + std::to_string(p) + ")" : std::string();
+        if (flags[p] == 1.0) return fail(CCSDT_EINVAL, "non-finite orbital energy" + where);
+        if (flags[p] != 0.0)
+            return fail(CCSDT_EDENOM, "max(eps_o) >= min(eps_v): denominators must be negative" + where);
+    }
+    return CCSDT_OK;
+}
+
+// Batched submission through a captured graph.  The graph is rebuilt when
+// the problem list, the precision or any workspace buffer (ctx->gen) changes,
+// and replayed otherwise: a replay reads the inputs' current contents.
+int energy_graph(ccsdt_context* ctx, int nprob, const ccsdt_problem* probs, int prec, hipStream_t s,
+                 double* out_host) {
+    GraphEntry& G = ctx->graph;
+    if (!graph_matches(ctx, nprob, probs, prec)) {
+        graph_reset(G);
+        Plan P;
+        std::vector<int> tb;
+        whole_problem_plan(P, nprob, probs, tb);
+        CHK(plan_pipeline(ctx, P, prec));
+        CHK(ensure(ctx, ctx->tripbeg, sizeof(int) * (nprob + 1), "triple ranges"));
+        CHK(ensure(ctx, ctx->out, sizeof(double) * 4 * nprob, "result"));
+        CHK(ensure(ctx, ctx->pdesc, sizeof(GapDesc) * nprob, "problem table"));
+        const GraphHostLayout h = graph_host_layout(P.slots.size(), nprob);
+        CHK(ensure_host(&G.host, &G.host_bytes, h.bytes));
+        char* host = static_cast<char*>(G.host);
+        if (!P.slots.empty()) std::memcpy(host + h.slots_off, P.slots.data(), P.slots.size() * sizeof(Slot));
+        std::memcpy(host + h.tb_off, tb.data(), sizeof(int) * (nprob + 1));
+        GapDesc* desc = reinterpret_cast<GapDesc*>(host + h.desc_off);
+        for (int p = 0; p < nprob; ++p) desc[p] = {probs[p].eps_o, probs[p].eps_v, probs[p].nocc, probs[p].nvirt};
+        CHK(capture_batched(ctx, P, nprob, prec, host, h));
+        G.layout_out = h.out_off;
+        G.prec = prec;
+        G.probs.assign(probs, probs + nprob);
+        G.gen = ctx->gen;
+        G.valid = true;
+        ctx->n_captures++;
+    }
+    HIPCHK(hipGraphLaunch(G.exec, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->n_replays++;
+    const double* res = reinterpret_cast<const double*>(static_cast<char*>(G.host) + G.layout_out);
+    CHK(check_flags(res + 3 * nprob, nprob));
+    std::memcpy(out_host, res, sizeof(double) * 3 * nprob);
+    return CCSDT_OK;
+}
+
+// ---- autotuning ------------------------------------------------------------------
+// Contraction time (ms) of tile configuration cfg on the given triples.
+int time_cfg(ccsdt_context* ctx, const ccsdt_problem* prob, int prec, int cfg, const std::vector<TripRef>& trips,
+             hipStream_t s, double* ms) {
+    const bool was = ctx->profile;
+    ctx->profile = true;
+    ctx->forced_cfg = cfg;
+    const int64_t n0 = ctx->prof_n[K_CONTRACT];
+    const double t0 = ctx->prof_ms[K_CONTRACT];
+    prof_start_call(ctx);
+    Plan P;
+    P.probs.assign(1, ProbLayout{});
+    P.probs[0].p = *prob;
+    P.trips = trips;
+    P.n_out = trips.size();
+    int rc = run_pipeline(ctx, P, prec, s, nullptr);
+    if (rc == CCSDT_OK) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            rc = fail(CCSDT_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+        }
+    }
+    if (rc == CCSDT_OK) rc = prof_collect(ctx);
+    *ms = ctx->prof_ms[K_CONTRACT] - t0;
+    // the tuning launches are not part of the caller's profile
+    ctx->prof_n[K_CONTRACT] = n0;
+    ctx->prof_ms[K_CONTRACT] = t0;
+    ctx->forced_cfg = -1;
+    ctx->profile = was;
+    return rc;
 }
 
 }  // namespace
@@ -425,7 +645,11 @@ int ccsdt_context_create(ccsdt_context** ctx_out) {
 
 int ccsdt_context_destroy(ccsdt_context* ctx) {
     if (!ctx) return fail(CCSDT_EINVAL, "null context");
-    DevBuf* bufs[] = {&ctx->gc, &ctx->tc, &ctx->w, &ctx->part, &ctx->etrip, &ctx->slots, &ctx->out, &ctx->tripbeg};
+    graph_reset(ctx->graph);
+    if (ctx->graph.host) (void)hipHostFree(ctx->graph.host);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    DevBuf* bufs[] = {&ctx->gc, &ctx->tc, &ctx->w, &ctx->part, &ctx->etrip, &ctx->slots, &ctx->out, &ctx->tripbeg,
+                      &ctx->pdesc};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->host_out) (void)hipHostFree(ctx->host_out);
@@ -465,28 +689,19 @@ static int energy_many(ccsdt_context* ctx, int nprob, const ccsdt_problem* probs
     if (!out_host) return fail(CCSDT_EINVAL, "null output");
     if (nprob < 1 || !probs) return fail(CCSDT_EINVAL, "no problems");
     CHK(check_prec(prec));
-    prof_start_call(ctx);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    std::vector<ProbLayout> L(nprob);
-    std::vector<TripRef> trips;
-    std::vector<int> tb(nprob + 1, 0);
-    for (int p = 0; p < nprob; ++p) {
-        CHK(check_problem(&probs[p], nprob > 1 ? p : -1));
-        CHK(check_gap(&probs[p], s, nprob > 1 ? p : -1));
-        L[p].p = probs[p];
-        const int o = probs[p].nocc;
-        tb[p] = (int)trips.size();
-        for (int i = 0; i < o; ++i)
-            for (int j = i; j < o; ++j)
-                for (int k = j; k < o; ++k) {
-                    const int m = multiplicity(i, j, k);
-                    if (m) trips.push_back({p, i, j, k, m, (int)trips.size()});
-                }
-    }
-    tb[nprob] = (int)trips.size();
-    CHK(run_pipeline(ctx, L, trips, prec, s, trips.size(), nullptr));
+    for (int p = 0; p < nprob; ++p) CHK(check_problem(&probs[p], nprob > 1 ? p : -1));
+    if (nprob > 1 && !ctx->profile && env_int("CCSDT_GRAPH", 1) != 0)
+        return energy_graph(ctx, nprob, probs, prec, s, out_host);
+
+    prof_start_call(ctx);
+    for (int p = 0; p < nprob; ++p) CHK(check_gap(&probs[p], s, nprob > 1 ? p : -1));
+    Plan P;
+    std::vector<int> tb;
+    whole_problem_plan(P, nprob, probs, tb);
+    CHK(run_pipeline(ctx, P, prec, s, nullptr));
     CHK(ensure(ctx, ctx->tripbeg, sizeof(int) * (nprob + 1), "triple ranges"));
-    CHK(ensure(ctx, ctx->out, sizeof(double) * 3 * nprob, "result"));
+    CHK(ensure(ctx, ctx->out, sizeof(double) * 4 * nprob, "result"));
     CHK(ensure_host((void**)&ctx->host_tb, &ctx->host_tb_bytes, sizeof(int) * (nprob + 1)));
     CHK(ensure_host((void**)&ctx->host_out, &ctx->host_out_bytes, sizeof(double) * 3 * nprob));
     std::memcpy(ctx->host_tb, tb.data(), sizeof(int) * (nprob + 1));
@@ -533,23 +748,24 @@ int ccsdt_triple_energies(ccsdt_context* ctx, const ccsdt_problem* prob, int pre
     if (ntrip < 1) return fail(CCSDT_EINVAL, "ntrip must be >= 1");
     CHK(check_prec(precision));
     CHK(check_problem(prob, -1));
-    prof_start_call(ctx);
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    CHK(check_gap(prob, s, -1));
     const int o = prob->nocc;
-    std::vector<TripRef> trips;
+    Plan P;
     std::vector<int> zero_rows;
     for (int t = 0; t < ntrip; ++t) {
         const int i = ijk_host[3 * t], j = ijk_host[3 * t + 1], k = ijk_host[3 * t + 2];
         if (!(0 <= i && i <= j && j <= k && k < o))
             return fail(CCSDT_EINVAL, "triple " + std::to_string(t) + " is not 0 <= i <= j <= k < nocc");
         const int m = multiplicity(i, j, k);
-        if (m) trips.push_back({0, i, j, k, m, t});
+        if (m) P.trips.push_back({0, i, j, k, m, t});
         else zero_rows.push_back(t);
     }
-    std::vector<ProbLayout> L(1);
-    L[0].p = *prob;
-    CHK(run_pipeline(ctx, L, trips, precision, s, (size_t)ntrip, nullptr));
+    prof_start_call(ctx);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    CHK(check_gap(prob, s, -1));
+    P.probs.assign(1, ProbLayout{});
+    P.probs[0].p = *prob;
+    P.n_out = (size_t)ntrip;
+    CHK(run_pipeline(ctx, P, precision, s, nullptr));
     CHK(ensure_host((void**)&ctx->host_out, &ctx->host_out_bytes, sizeof(double) * 3 * ntrip));
     HIPCHK(hipMemcpyAsync(ctx->host_out, ctx->etrip.p, sizeof(double) * 3 * ntrip, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -570,9 +786,12 @@ int ccsdt_debug_w(ccsdt_context* ctx, const ccsdt_problem* prob, int precision, 
     prof_start_call(ctx);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const int64_t v = prob->nvirt;
-    std::vector<ProbLayout> L(1);
-    L[0].p = *prob;
-    std::vector<TripRef> trips{{0, i, j, k, std::max(1, multiplicity(i, j, k)), 0}};
+    Plan P;
+    P.probs.assign(1, ProbLayout{});
+    P.probs[0].p = *prob;
+    P.trips = {{0, i, j, k, std::max(1, multiplicity(i, j, k)), 0}};
+    P.n_out = 1;
+    P.one_per_chunk = true;
     DevBuf tmp;
     const size_t bytes = (size_t)(v * v * v) * sizeof(double);
     hipError_t e = hipMalloc(&tmp.p, bytes);
@@ -580,7 +799,7 @@ int ccsdt_debug_w(ccsdt_context* ctx, const ccsdt_problem* prob, int precision, 
         (void)hipGetLastError();
         return fail(CCSDT_ENOMEM, "hipMalloc for debug W failed");
     }
-    int rc = run_pipeline(ctx, L, trips, precision, s, 1, static_cast<double*>(tmp.p));
+    int rc = run_pipeline(ctx, P, precision, s, static_cast<double*>(tmp.p));
     if (rc == CCSDT_OK) {
         e = hipMemcpyAsync(w_host, tmp.p, bytes, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -588,10 +807,69 @@ int ccsdt_debug_w(ccsdt_context* ctx, const ccsdt_problem* prob, int precision, 
             (void)hipGetLastError();
             rc = fail(CCSDT_EHIP, std::string("copy of W failed: ") + hipGetErrorString(e));
         }
+    } else {
+        (void)hipStreamSynchronize(s);
+        (void)hipGetLastError();
     }
     (void)hipFree(tmp.p);
     if (rc == CCSDT_OK) rc = prof_collect(ctx);
     return rc;
+}
+
+int ccsdt_autotune(ccsdt_context* ctx, const ccsdt_problem* prob, int precision, void* hip_stream, int* cfg_out) {
+    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    CHK(check_prec(precision));
+    CHK(check_problem(prob, -1));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    CHK(check_gap(prob, s, -1));
+    // up to four distinct triples (i<j<k) of the problem; two-equal triples
+    // when nocc < 3
+    const int o = prob->nocc;
+    std::vector<TripRef> trips;
+    for (int k = 2; k < o && trips.size() < 4; ++k) trips.push_back({0, 0, 1, k, 6, (int)trips.size()});
+    for (int i = 0; i + 1 < o && trips.size() < 4; ++i) trips.push_back({0, i, i + 1, i + 1, 3, (int)trips.size()});
+    if (trips.empty()) return fail(CCSDT_EINVAL, "nocc = 1 has no triples to time");
+    int best = -1;
+    double best_ms = 0.0;
+    for (int cfg = 0; cfg < NTILE_CFG; ++cfg) {
+        double ms = 0.0;
+        CHK(time_cfg(ctx, prob, precision, cfg, trips, s, &ms));   // first run loads the kernel
+        CHK(time_cfg(ctx, prob, precision, cfg, trips, s, &ms));
+        if (best < 0 || ms < best_ms) {
+            best = cfg;
+            best_ms = ms;
+        }
+    }
+    ctx->plans[{precision, v_bucket(prob->nvirt)}] = best;
+    ++ctx->gen;   // captured graphs embed the tile choice
+    if (cfg_out) *cfg_out = best;
+    return CCSDT_OK;
+}
+
+int ccsdt_plan_get(ccsdt_context* ctx, int precision, int nvirt, int* cfg_out) {
+    if (!ctx || !cfg_out) return fail(CCSDT_EINVAL, "null argument");
+    CHK(check_prec(precision));
+    if (nvirt < 1) return fail(CCSDT_EINVAL, "nvirt must be >= 1");
+    *cfg_out = tile_cfg_for(ctx, precision, nvirt);
+    return CCSDT_OK;
+}
+
+int ccsdt_plan_set(ccsdt_context* ctx, int precision, int nvirt, int cfg) {
+    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    CHK(check_prec(precision));
+    if (nvirt < 1) return fail(CCSDT_EINVAL, "nvirt must be >= 1");
+    if (cfg < -1 || cfg >= NTILE_CFG) return fail(CCSDT_EINVAL, "tile configuration out of range");
+    if (cfg < 0) ctx->plans.erase({precision, v_bucket(nvirt)});
+    else ctx->plans[{precision, v_bucket(nvirt)}] = cfg;
+    ++ctx->gen;
+    return CCSDT_OK;
+}
+
+int ccsdt_graph_stats(ccsdt_context* ctx, int64_t* captures, int64_t* replays) {
+    if (!ctx || !captures || !replays) return fail(CCSDT_EINVAL, "null argument");
+    *captures = ctx->n_captures;
+    *replays = ctx->n_replays;
+    return CCSDT_OK;
 }
 
 }  // extern "C"

@@ -40,7 +40,7 @@ struct Slot {
     int i, j, k, mult;        // triple and its multiplicity (6 or 3)
     int o, v, Kp, prob;       // sizes and problem index
     int tiles_m, tiles_n;     // ceil(v / tile edge) along m and n
-    int nbw, pad_;            // W blocks per dimension, ceil(v / WB)
+    int nbw, bgroups;         // W blocks per dimension, ceil(v / WB); batch groups per pass
     int a_begin, b_begin;     // first contraction workgroup of this slot; unused
     int e_begin, trip_index;  // first energy workgroup; index into e_trip
     int64_t part_begin;       // first partial-sum entry (2 doubles each)
@@ -71,21 +71,38 @@ hipError_t launch_final_reduce(const int* d_trip_begin, int nprob, const double*
 // W (any precision, blocked layout) of one slot as dense float64 [a][b][c].
 hipError_t launch_widen_w(int prec, const void* w, int v, double* out, hipStream_t s);
 
+// Orbital energies of one problem, for the denominator sign check.
+struct GapDesc {
+    const double* eps_o;
+    const double* eps_v;
+    int o, v;
+};
+// flag[p] = 0 if every eps_o and eps_v of problem p is finite and
+// max(eps_o) < min(eps_v) (all denominators negative), 1 if a value is not
+// finite, 2 if the gap is not positive.
+hipError_t launch_gap_check(const GapDesc* d_desc, int nprob, double* flag, hipStream_t s);
+
 __host__ __device__ inline int64_t w_index(int a, int b, int c, int nb) {
     return ((((int64_t)(a >> 4) * nb + (b >> 4)) * nb + (c >> 4)) << 12) + ((a & 15) << 8) + ((b & 15) << 4) + (c & 15);
 }
 
 // Contraction tile configurations (workgroup tile BM x BN over the (row, col)
-// plane of one batch index).  0-2: operands loaded straight from global
-// memory into MFMA fragments, 2x2 waves.  3-5: operands staged through
-// double-buffered LDS, 2x2 waves.
-// 6-7: as 3-4 with operands written straight from global memory into LDS
-// (global_load_lds), without a register round trip.
-struct TileCfg { int bm, bn, lds; };
-constexpr int NTILE_CFG = 8;
+// plane of nbat consecutive batch indices).  0-2: operands loaded straight
+// from global memory into MFMA fragments, 2x2 waves.  3-5: operands staged
+// through double-buffered LDS, 2x2 waves.  6-7: as 3-4 with operands written
+// straight from global memory into LDS (global_load_lds), without a register
+// round trip.  8-9: direct-to-LDS staging with two batch indices per
+// workgroup sharing the batch-independent operand rows (8: four waves of
+// 128x64, 9: eight waves of 64x64).  10-11: as 8-9 with the fragments of the
+// next stage read into registers while the current stage's MFMAs run.
+struct TileCfg { int bm, bn, lds, nbat; };
+constexpr int NTILE_CFG = 12;
 constexpr TileCfg TILE_CFGS[NTILE_CFG] = {
-    {64, 64, 0}, {128, 64, 0}, {128, 128, 0}, {128, 128, 1}, {128, 256, 1}, {64, 128, 1}, {128, 128, 2}, {128, 256, 2}};
+    {64, 64, 0, 1},   {128, 64, 0, 1},  {128, 128, 0, 1}, {128, 128, 1, 1}, {128, 256, 1, 1},
+    {64, 128, 1, 1},  {128, 128, 2, 1}, {128, 256, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 2},
+    {128, 128, 2, 2}, {128, 128, 2, 2}};
 inline int tile_m(int cfg) { return TILE_CFGS[cfg].bm; }
 inline int tile_n(int cfg) { return TILE_CFGS[cfg].bn; }
+inline int tile_nbat(int cfg) { return TILE_CFGS[cfg].nbat; }
 
 }  // namespace ccsdt

@@ -175,8 +175,9 @@ __device__ __forceinline__ void store_tile(const Slot* S, int pass, int beta, in
     }
 }
 
-// Locate this workgroup's slot, pass, batch index and tile.  Within a slot
-// the pass-A workgroups come first, then the pass-B ones.
+// Locate this workgroup's slot, pass, batch group and tile.  Within a slot
+// the pass-A workgroups come first, then the pass-B ones.  A batch group is
+// one batch index, or nbat consecutive ones for the batch-shared kernel.
 __device__ __forceinline__ const Slot* find_slot(const Slot* slots, int nslot, int bid, int& pass, int& beta,
                                                  int& tmi, int& tni) {
     int lo = 0, hi = nslot - 1;
@@ -188,7 +189,7 @@ __device__ __forceinline__ const Slot* find_slot(const Slot* slots, int nslot, i
     const int tn = S->tiles_n;
     const int per_beta = S->tiles_m * tn;
     int local = bid - S->a_begin;
-    const int per_pass = S->v * per_beta;
+    const int per_pass = S->bgroups * per_beta;
     pass = local >= per_pass;
     local -= pass * per_pass;
     beta = local / per_beta;
@@ -440,6 +441,302 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
     if (active) store_tile<P, MB, NB>(S, pass, beta, m0, n0, vm, vn, lane, acc);
 }
 
+// Batch-shared variant.  In every segment exactly one operand depends on the
+// batch index (rows of G) and the other does not (rows of T), so a
+// workgroup that takes NBAT consecutive batch indices stages the shared
+// operand once for all of them: per stage, 128 shared rows followed by 128
+// batch-dependent rows per batch index, in the chunk order and swizzle of
+// contract_lds_kernel, written straight from global memory (global_load_lds).
+// Wave w computes the (WTM x WTN) sub-tile w % WPB of the 128 x 128 tile of
+// batch index beta0 + w / WPB.
+template <class P, int WTM, int WTN, int NBAT, int MINB>
+__global__ __launch_bounds__(NBAT * (128 / WTM) * (128 / WTN) * 64, MINB) void contract_bat_kernel(
+    const Slot* __restrict__ slots, int nslot, int total) {
+    constexpr int BM = 128, BN = 128;
+    constexpr int WPB = (BM / WTM) * (BN / WTN);
+    constexpr int NT = 64 * NBAT * WPB;
+    constexpr int RS = 128;
+    constexpr int ROWS = 128 * (1 + NBAT);
+    constexpr int TPR = RS / 16;
+    constexpr int RPP = NT / TPR;
+    constexpr int NP = ROWS / RPP;
+    static_assert(ROWS % RPP == 0, "rows must split evenly over the threads");
+    static_assert(RPP % 8 == 0, "staging rows must keep the swizzle bits");
+    constexpr int MB = WTM / 16, NB = WTN / 16;
+    __shared__ __attribute__((aligned(16))) char lds[2 * ROWS * RS];
+
+    const int bid = xcd_remap(blockIdx.x, total);
+    int pass, bgrp, tmi, tni;
+    const Slot* S = find_slot(slots, nslot, bid, pass, bgrp, tmi, tni);
+    const int v = S->v, o = S->o, Kp = S->Kp;
+    const int mt0 = tmi * BM, nt0 = tni * BN;
+    const int beta0 = bgrp * NBAT;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wb = wave / WPB, wsub = wave % WPB;
+    const int wm = wsub / (BN / WTN), wn = wsub % (BN / WTN);
+    const int beta = beta0 + wb;
+    const int m0 = mt0 + wm * WTM, n0 = nt0 + wn * WTN;
+    const int vm = beta < v ? max(0, min(MB, (v - m0 + 15) / 16)) : 0;
+    const int vn = max(0, min(NB, (v - n0 + 15) / 16));
+
+    const int64_t rowbytes = (int64_t)Kp * P::UNITS * sizeof(typename P::E);
+    const int csteps = (int)(rowbytes / RS);
+    const int nsteps = NSEG * csteps;
+    const char* G = static_cast<const char*>(S->gc);
+    const char* T = static_cast<const char*>(S->tc);
+    const int lrow = threadIdx.x / TPR;
+    const int pch = (lane & 7) ^ lds_swz(lrow);
+    const int src_col = (P::SPLIT ? (((pch & 3) << 1) | (pch >> 2)) : pch) * 16;
+    const int wave_row0 = wave * (64 / TPR);
+
+    // Source of each of this thread's stage rows for the current segment.
+    const char* rbase[NP];
+    typename P::Acc acc[MB][NB];
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = typename P::Acc{};
+
+    bool depA = true;  // segment's batch-dependent operand is A (rows) rather than B (cols)
+    auto set_rows = [&](int sg) {
+        const SegRows g = segment(pass, sg, S->i, S->j, S->k, o, v);
+        depA = g.aB != 0;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int r = lrow + p * RPP;
+            int64_t row;
+            if (r < 128) {  // shared operand
+                row = depA ? g.b0 + (int64_t)min(nt0 + r, v - 1) * g.bN : g.a0 + (int64_t)min(mt0 + r, v - 1) * g.aM;
+            } else {
+                const int bb = min(beta0 + (r - 128) / 128, v - 1), rr = (r - 128) % 128;
+                row = depA ? g.a0 + bb * g.aB + (int64_t)min(mt0 + rr, v - 1) * g.aM
+                           : g.b0 + bb * g.bB + (int64_t)min(nt0 + rr, v - 1) * g.bN;
+            }
+            const bool fromG = (r < 128) == !depA ? g.aG : g.bG;
+            rbase[p] = (fromG ? G : T) + row * rowbytes + src_col;
+        }
+    };
+    auto gload = [&](int c, int buf) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            char* dst = lds + buf * (ROWS * RS) + (wave_row0 + p * RPP) * RS;
+            __builtin_amdgcn_global_load_lds((const GLOBAL void*)gp(rbase[p] + (int64_t)c * RS),
+                                             (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+        }
+    };
+
+    set_rows(0);
+    gload(0, 0);
+    __syncthreads();
+    const bool active = vm > 0 && vn > 0;
+    bool dep_cur = depA;
+    int sg_next = 0, c_next = 0;
+    for (int step = 0; step < nsteps; ++step) {
+        const int buf = step & 1;
+        const bool dep_this = dep_cur;
+        if (step + 1 < nsteps && ++c_next == csteps) {
+            c_next = 0;
+            ++sg_next;
+            set_rows(sg_next);
+        }
+        gload(c_next, buf ^ 1);
+        dep_cur = depA;
+        __builtin_amdgcn_sched_barrier(0);
+        if (active) {
+            const char* st = lds + buf * (ROWS * RS);
+            const int arow = dep_this ? 128 * (1 + wb) + wm * WTM : wm * WTM;
+            const int brow = dep_this ? wn * WTN : 128 * (1 + wb) + wn * WTN;
+            const char* As = st + (arow + (lane & 15)) * RS;
+            const char* Bs = st + (brow + (lane & 15)) * RS;
+            const int g = lane >> 4;
+            const int sw = lds_swz(lane & 15);
+            if (vm == MB && vn == NB)
+                lds_stage<P, MB, NB, RS, true>(acc, As, Bs, g, sw, vm, vn);
+            else
+                lds_stage<P, MB, NB, RS, false>(acc, As, Bs, g, sw, vm, vn);
+        }
+        __syncthreads();
+    }
+    if (active) store_tile<P, MB, NB>(S, pass, beta, m0, n0, vm, vn, lane, acc);
+}
+
+// Fragments of one LDS stage for a wave's MB x NB blocks.
+template <class P, int MB, int NB>
+struct StageFrags {
+    typename P::Frag a[P::NSUB][MB], b[P::NSUB][NB];
+};
+
+template <class P, int MB, int NB, int RS>
+__device__ __forceinline__ void read_frags(StageFrags<P, MB, NB>& f, const char* As, const char* Bs, int g, int sw) {
+#pragma unroll
+    for (int sub = 0; sub < P::NSUB; ++sub) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) P::load_lds(f.b[sub][b], Bs + b * 16 * RS, g, sub, sw);
+#pragma unroll
+        for (int a = 0; a < MB; ++a) P::load_lds(f.a[sub][a], As + a * 16 * RS, g, sub, sw);
+    }
+}
+
+// MFMAs of one stage from registers (cur) while the fragments of the next
+// stage are read from LDS into nxt; the reads are spread over the MFMA
+// stream (one fragment read per row of blocks) so that LDS latency hides
+// behind matrix work.
+template <class P, int MB, int NB, int RS, bool FULL>
+__device__ __forceinline__ void mma_stage_overlap(typename P::Acc (&acc)[MB][NB], const StageFrags<P, MB, NB>& cur,
+                                                  StageFrags<P, MB, NB>& nxt, const char* As, const char* Bs, int g,
+                                                  int sw, int vm, int vn) {
+#pragma unroll
+    for (int sub = 0; sub < P::NSUB; ++sub) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) P::load_lds(nxt.b[sub][b], Bs + b * 16 * RS, g, sub, sw);
+#pragma unroll
+        for (int a = 0; a < MB; ++a) {
+            P::load_lds(nxt.a[sub][a], As + a * 16 * RS, g, sub, sw);
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if (FULL || (a < vm && b < vn)) P::mma(acc[a][b], cur.a[sub][a], cur.b[sub][b]);
+        }
+    }
+}
+
+// Batch-shared kernel with register-prefetched fragments.  Stage s of the K
+// loop lives in LDS buffer s % 2; it is requested (global_load_lds) two
+// steps before its MFMAs run, its fragments are read into registers during
+// the step before, interleaved with that step's MFMAs, and the MFMAs of a
+// step run from registers only.  One barrier per step (it waits for the
+// wave's outstanding loads and LDS reads): after it, stage s + 1 has landed
+// and every wave holds stage s in registers, so the request for stage s + 2
+// may overwrite buffer s % 2.  Tiles, rows and swizzle as
+// contract_bat_kernel.
+template <class P, int WTM, int WTN, int NBAT, int MINB>
+__global__ __launch_bounds__(NBAT * (128 / WTM) * (128 / WTN) * 64, MINB) void contract_pipe_kernel(
+    const Slot* __restrict__ slots, int nslot, int total) {
+    constexpr int BM = 128, BN = 128;
+    constexpr int WPB = (BM / WTM) * (BN / WTN);
+    constexpr int NT = 64 * NBAT * WPB;
+    constexpr int RS = 128;
+    constexpr int ROWS = 128 * (1 + NBAT);
+    constexpr int TPR = RS / 16;
+    constexpr int RPP = NT / TPR;
+    constexpr int NP = ROWS / RPP;
+    static_assert(ROWS % RPP == 0, "rows must split evenly over the threads");
+    static_assert(RPP % 8 == 0, "staging rows must keep the swizzle bits");
+    constexpr int MB = WTM / 16, NB = WTN / 16;
+    __shared__ __attribute__((aligned(16))) char lds[2 * ROWS * RS];
+
+    const int bid = xcd_remap(blockIdx.x, total);
+    int pass, bgrp, tmi, tni;
+    const Slot* S = find_slot(slots, nslot, bid, pass, bgrp, tmi, tni);
+    const int v = S->v, o = S->o, Kp = S->Kp;
+    const int mt0 = tmi * BM, nt0 = tni * BN;
+    const int beta0 = bgrp * NBAT;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wb = wave / WPB, wsub = wave % WPB;
+    const int wm = wsub / (BN / WTN), wn = wsub % (BN / WTN);
+    const int beta = beta0 + wb;
+    const int m0 = mt0 + wm * WTM, n0 = nt0 + wn * WTN;
+    const int vm = beta < v ? max(0, min(MB, (v - m0 + 15) / 16)) : 0;
+    const int vn = max(0, min(NB, (v - n0 + 15) / 16));
+
+    const int64_t rowbytes = (int64_t)Kp * P::UNITS * sizeof(typename P::E);
+    const int csteps = (int)(rowbytes / RS);
+    const int nsteps = NSEG * csteps;
+    const char* G = static_cast<const char*>(S->gc);
+    const char* T = static_cast<const char*>(S->tc);
+    const int lrow = threadIdx.x / TPR;
+    const int pch = (lane & 7) ^ lds_swz(lrow);
+    const int src_col = (P::SPLIT ? (((pch & 3) << 1) | (pch >> 2)) : pch) * 16;
+    const int wave_row0 = wave * (64 / TPR);
+
+    const char* rbase[NP];
+    typename P::Acc acc[MB][NB];
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = typename P::Acc{};
+
+    // In both passes the batch-dependent operand is A in segment 0 and B in
+    // segments 1 and 2.
+    auto set_rows = [&](int sg) {
+        const SegRows g = segment(pass, sg, S->i, S->j, S->k, o, v);
+        const bool depA = sg == 0;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int r = lrow + p * RPP;
+            int64_t row;
+            if (r < 128) {
+                row = depA ? g.b0 + (int64_t)min(nt0 + r, v - 1) * g.bN : g.a0 + (int64_t)min(mt0 + r, v - 1) * g.aM;
+            } else {
+                const int bb = min(beta0 + (r - 128) / 128, v - 1), rr = (r - 128) % 128;
+                row = depA ? g.a0 + bb * g.aB + (int64_t)min(mt0 + rr, v - 1) * g.aM
+                           : g.b0 + bb * g.bB + (int64_t)min(nt0 + rr, v - 1) * g.bN;
+            }
+            const bool fromG = (r < 128) == !depA ? g.aG : g.bG;
+            rbase[p] = (fromG ? G : T) + row * rowbytes + src_col;
+        }
+    };
+    // Request the next stage (past the last one, the last chunk again) into buf.
+    int ld_sg = 0, ld_c = -1;
+    auto request = [&](int buf) {
+        if (!(ld_sg == NSEG - 1 && ld_c == csteps - 1)) {
+            if (++ld_c == csteps) {
+                ld_c = 0;
+                ++ld_sg;
+                set_rows(ld_sg);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            char* dst = lds + buf * (ROWS * RS) + (wave_row0 + p * RPP) * RS;
+            __builtin_amdgcn_global_load_lds((const GLOBAL void*)gp(rbase[p] + (int64_t)ld_c * RS),
+                                             (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+        }
+    };
+    const int g = lane >> 4;
+    const int sw = lds_swz(lane & 15);
+    // this wave's A / B fragment rows of stage `stage` in buffer `buf`
+    auto a_ptr = [&](int stage, int buf) {
+        const int arow = stage < csteps ? 128 * (1 + wb) + wm * WTM : wm * WTM;
+        return lds + buf * (ROWS * RS) + (arow + (lane & 15)) * RS;
+    };
+    auto b_ptr = [&](int stage, int buf) {
+        const int brow = stage < csteps ? wn * WTN : 128 * (1 + wb) + wn * WTN;
+        return lds + buf * (ROWS * RS) + (brow + (lane & 15)) * RS;
+    };
+
+    set_rows(0);
+    request(0);
+    request(1);
+    __syncthreads();
+    StageFrags<P, MB, NB> f0, f1;
+    read_frags<P, MB, NB, RS>(f0, a_ptr(0, 0), b_ptr(0, 0), g, sw);
+    const bool active = vm > 0 && vn > 0;
+    const bool full = vm == MB && vn == NB;
+
+    for (int step = 0; step < nsteps; step += 2) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int st = step + h;
+            if (h == 1 && st >= nsteps) break;
+            __syncthreads();
+            request(h);  // stage st + 2 into buffer st % 2 (= h)
+            __builtin_amdgcn_sched_barrier(0);
+            const int nst = min(st + 1, nsteps - 1);
+            const char* As = a_ptr(nst, h ^ 1);
+            const char* Bs = b_ptr(nst, h ^ 1);
+            if (active) {
+                if (full)
+                    mma_stage_overlap<P, MB, NB, RS, true>(acc, h == 0 ? f0 : f1, h == 0 ? f1 : f0, As, Bs, g, sw,
+                                                           vm, vn);
+                else
+                    mma_stage_overlap<P, MB, NB, RS, false>(acc, h == 0 ? f0 : f1, h == 0 ? f1 : f0, As, Bs, g, sw,
+                                                            vm, vn);
+            }
+        }
+    }
+    if (active) store_tile<P, MB, NB>(S, pass, beta, m0, n0, vm, vn, lane, acc);
+}
+
 template <class P>
 static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int total, hipStream_t s) {
     switch (cfg) {
@@ -451,6 +748,10 @@ static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int tot
         case 5: hipLaunchKernelGGL((contract_lds_kernel<P, 32, 64, 128, 2, false>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 6: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 64, 128, 2, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 7: hipLaunchKernelGGL((contract_lds_kernel<P, 64, 128, 128, 1, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 8: hipLaunchKernelGGL((contract_bat_kernel<P, 128, 64, 2, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 9: hipLaunchKernelGGL((contract_bat_kernel<P, 64, 64, 2, 1>), dim3(total), dim3(512), 0, s, d_slots, nslot, total); break;
+        case 10: hipLaunchKernelGGL((contract_pipe_kernel<P, 128, 64, 2, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 11: hipLaunchKernelGGL((contract_pipe_kernel<P, 64, 64, 2, 1>), dim3(total), dim3(512), 0, s, d_slots, nslot, total); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -288,6 +288,39 @@ __global__ __launch_bounds__(256) void final_reduce_kernel(const int* __restrict
     }
 }
 
+__global__ __launch_bounds__(256) void gap_check_kernel(const GapDesc* __restrict__ desc,
+                                                        double* __restrict__ flag) {
+    __shared__ double smax[256], smin[256];
+    __shared__ int sbad;
+    const GapDesc g = desc[blockIdx.x];
+    if (threadIdx.x == 0) sbad = 0;
+    __syncthreads();
+    double mo = -INFINITY, mv = INFINITY;
+    int bad = 0;
+    for (int n = threadIdx.x; n < g.o; n += 256) {
+        const double x = g.eps_o[n];
+        bad |= !isfinite(x);
+        mo = fmax(mo, x);
+    }
+    for (int n = threadIdx.x; n < g.v; n += 256) {
+        const double x = g.eps_v[n];
+        bad |= !isfinite(x);
+        mv = fmin(mv, x);
+    }
+    smax[threadIdx.x] = mo;
+    smin[threadIdx.x] = mv;
+    if (bad) atomicOr(&sbad, 1);
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + h]);
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) flag[blockIdx.x] = sbad ? 1.0 : (smax[0] < smin[0] ? 0.0 : 2.0);
+}
+
 template <class WT>
 __global__ void widen_kernel(const WT* __restrict__ w, int v, double* __restrict__ out) {
     const int nb = (v + WB - 1) / WB;
@@ -318,6 +351,11 @@ hipError_t launch_slot_reduce(const Slot* d_slots, int nslot, int, const double*
 hipError_t launch_final_reduce(const int* d_trip_begin, int nprob, const double* e_trip, double* out,
                                hipStream_t s) {
     hipLaunchKernelGGL(final_reduce_kernel, dim3(nprob), dim3(256), 0, s, d_trip_begin, e_trip, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gap_check(const GapDesc* d_desc, int nprob, double* flag, hipStream_t s) {
+    hipLaunchKernelGGL(gap_check_kernel, dim3(nprob), dim3(256), 0, s, d_desc, flag);
     return hipGetLastError();
 }
 

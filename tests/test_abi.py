@@ -57,3 +57,14 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.ccsdt_energy(None, None, 0, None, out) == -1
     assert lib.ccsdt_triples_energy(6, 30, *([None] * 7), 0, None, None) == -1
     assert lib.ccsdt_profile_get(None, 0, None, None) == -1
+
+
+def test_plan_and_graph_entry_points_reject_null_context():
+    lib = _lib()
+    cfg = ctypes.c_int()
+    assert lib.ccsdt_autotune(None, None, 0, None, ctypes.byref(cfg)) == -1
+    assert lib.ccsdt_plan_get(None, 0, 100, ctypes.byref(cfg)) == -1
+    assert lib.ccsdt_plan_set(None, 0, 100, 0) == -1
+    c, r = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.ccsdt_graph_stats(None, ctypes.byref(c), ctypes.byref(r)) == -1
+    assert "null" in lib.ccsdt_last_error().decode()

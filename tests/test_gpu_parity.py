@@ -170,7 +170,7 @@ def tile_cases():
     return cases
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("cfg", list(range(12)))
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_every_tile_config(ctx, tile_cases, cfg, prec, monkeypatch):
     monkeypatch.setenv("CCSDT_TILE", str(cfg))
