@@ -143,6 +143,36 @@ int ccsdt_debug_w(ccsdt_context* ctx, const ccsdt_problem* prob, int precision,
 int ccsdt_energy_batched(ccsdt_context* ctx, int nprob, const ccsdt_problem* probs_host,
                          int precision, void* hip_stream, double* out_host);
 
+/* Density-fitted form of a problem (paper Sec. 2.1, eq. eri_sym_decomp):
+ * instead of the o*v^3 block vvvo, the caller passes the factors of
+ *   (ab|ci) = sum_Q B^Q_ab B^Q_ci
+ * with the auxiliary index fastest:
+ *   bvv[a][b][Q] = B^Q_ab   (v*v*naux),   bvo[c][i][Q] = B^Q_ci   (v*o*naux).
+ * The library assembles the (vv|vo) part of its packed operand on FP64
+ * matrix cores (rounded to the working precision afterwards), so that
+ * device memory holds B (C3: 5.5 GB) rather than vvvo (69 GB).  The other
+ * fields mean what they mean in ccsdt_problem; 1 <= naux <= 65536. */
+typedef struct ccsdt_problem_df {
+    int nocc;
+    int nvirt;
+    int naux;
+    const double* eps_o;
+    const double* eps_v;
+    const double* t1;
+    const double* t2;
+    const double* bvv;
+    const double* bvo;
+    const double* ovoo;
+    const double* ovov;
+} ccsdt_problem_df;
+
+/* ccsdt_energy and ccsdt_triple_energies for a density-fitted problem. */
+int ccsdt_energy_df(ccsdt_context* ctx, const ccsdt_problem_df* prob, int precision,
+                    void* hip_stream, double* out_host);
+int ccsdt_triple_energies_df(ccsdt_context* ctx, const ccsdt_problem_df* prob, int precision,
+                             int ntrip, const int* ijk_host, void* hip_stream,
+                             double* out_host);
+
 /* Tile plans.  The contraction kernel has NTILE = 12 tile configurations
  * (workgroup tile shape, operand staging through registers or LDS, direct
  * global-to-LDS loads, one or two batch indices per workgroup, fragment
@@ -177,7 +207,8 @@ int ccsdt_graph_stats(ccsdt_context* ctx, int64_t* captures, int64_t* replays);
  * by HIP events on the launch stream, and ccsdt_profile_get returns the
  * number of launches and their summed duration (ms) since the last reset.
  * Classes: 0 pack, 1 contraction (both passes: the six permutation terms of
- * W for every triple of a chunk), 2 energy, 3 reductions. */
+ * W for every triple of a chunk), 2 energy, 3 reductions, 4 DF assembly of
+ * the (vv|vo) operand. */
 int ccsdt_profile_enable(ccsdt_context* ctx, int on);
 int ccsdt_profile_get(ccsdt_context* ctx, int kernel_class, int64_t* launches,
                       double* total_ms);

@@ -6,3 +6,4 @@ import this package; the library never does, and the two share no code.
 from .triples import (triples_energy, triple_restricted, triple_literal, triple_list,
                       multiplicity, w_tensor, z_tensor, d_tensor, x_piece, problem_energy)
 from .spin_orbital import spin_orbital_triples, connected_antisymmetry_defect
+from .df import vvvo_from_df, triples_energy_df, triple_restricted_df

@@ -17,12 +17,14 @@ FP64, FP32, BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 STATUS = {0: "CCSDT_OK", -1: "CCSDT_EINVAL", -2: "CCSDT_ENOMEM", -3: "CCSDT_EHIP",
           -4: "CCSDT_EUNSUPPORTED", -5: "CCSDT_EDENOM"}
-KERNEL_CLASSES = {"pack": 0, "contract": 1, "energy": 2, "reduce": 3}
+KERNEL_CLASSES = {"pack": 0, "contract": 1, "energy": 2, "reduce": 3, "assemble": 4}
 FIELDS = ("eps_o", "eps_v", "t1", "t2", "vvvo", "ovoo", "ovov")
 EXPORTS = ("ccsdt_context_create", "ccsdt_context_destroy", "ccsdt_energy", "ccsdt_triples_energy",
            "ccsdt_triple_energies", "ccsdt_debug_w", "ccsdt_energy_batched", "ccsdt_profile_enable",
            "ccsdt_profile_get", "ccsdt_profile_reset", "ccsdt_flops", "ccsdt_last_error", "ccsdt_autotune",
-           "ccsdt_plan_get", "ccsdt_plan_set", "ccsdt_graph_stats")
+           "ccsdt_plan_get", "ccsdt_plan_set", "ccsdt_graph_stats", "ccsdt_energy_df",
+           "ccsdt_triple_energies_df")
+DF_FIELDS = ("eps_o", "eps_v", "t1", "t2", "bvv", "bvo", "ovoo", "ovov")
 NTILE_CFG = 12
 
 
@@ -35,6 +37,11 @@ class CcsdtError(RuntimeError):
 class Problem(ctypes.Structure):
     _fields_ = [("nocc", ctypes.c_int), ("nvirt", ctypes.c_int)] + \
                [(f, ctypes.c_void_p) for f in FIELDS]
+
+
+class ProblemDF(ctypes.Structure):
+    _fields_ = [("nocc", ctypes.c_int), ("nvirt", ctypes.c_int), ("naux", ctypes.c_int)] + \
+               [(f, ctypes.c_void_p) for f in DF_FIELDS]
 
 
 _lib = None
@@ -60,6 +67,9 @@ def load_library(path: str = LIB_PATH):
     lib.ccsdt_profile_enable.argtypes = [vp, ip]
     lib.ccsdt_profile_get.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int64), dp]
     lib.ccsdt_profile_reset.argtypes = [vp]
+    PD = ctypes.POINTER(ProblemDF)
+    lib.ccsdt_energy_df.argtypes = [vp, PD, ip, vp, dp]
+    lib.ccsdt_triple_energies_df.argtypes = [vp, PD, ip, ip, ctypes.POINTER(ctypes.c_int), vp, dp]
     lib.ccsdt_autotune.argtypes = [vp, P, ip, vp, ctypes.POINTER(ip)]
     lib.ccsdt_plan_get.argtypes = [vp, ip, ip, ctypes.POINTER(ip)]
     lib.ccsdt_plan_set.argtypes = [vp, ip, ip, ip]
@@ -89,17 +99,26 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def make_problem_struct(prob: dict) -> Problem:
-    """Problem struct from a dict of contiguous float64 device tensors."""
+def _dev_ptrs(prob: dict, fields) -> list:
     import torch
     vals = []
-    for f in FIELDS:
+    for f in fields:
         t = prob[f]
         if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous() \
                 or not t.is_cuda:
             raise ValueError(f"{f} must be a contiguous float64 tensor on the HIP device")
         vals.append(ctypes.c_void_p(t.data_ptr()))
-    return Problem(int(prob["nocc"]), int(prob["nvirt"]), *vals)
+    return vals
+
+
+def make_problem_struct(prob: dict) -> Problem:
+    """Problem struct from a dict of contiguous float64 device tensors."""
+    return Problem(int(prob["nocc"]), int(prob["nvirt"]), *_dev_ptrs(prob, FIELDS))
+
+
+def make_problem_df_struct(prob: dict) -> ProblemDF:
+    """ProblemDF struct (factors bvv[a][b][Q], bvo[c][i][Q]) from device tensors."""
+    return ProblemDF(int(prob["nocc"]), int(prob["nvirt"]), int(prob["naux"]), *_dev_ptrs(prob, DF_FIELDS))
 
 
 def flops(nocc: int, nvirt: int) -> float:
@@ -139,6 +158,23 @@ class Context:
         out = (ctypes.c_double * 3)()
         _check(load_library().ccsdt_energy(self._h, ctypes.byref(p), _prec(precision), _stream(stream), out))
         return out[0], out[1], out[2]
+
+    def energy_df(self, prob: dict, precision="fp64", stream=None):
+        """(E, E4, E5) of a density-fitted problem (factors instead of vvvo)."""
+        p = make_problem_df_struct(prob)
+        out = (ctypes.c_double * 3)()
+        _check(load_library().ccsdt_energy_df(self._h, ctypes.byref(p), _prec(precision), _stream(stream), out))
+        return out[0], out[1], out[2]
+
+    def triple_energies_df(self, prob: dict, triples, precision="fp64", stream=None):
+        """[(e, e4, e5)] per restricted triple of a density-fitted problem."""
+        flat = [int(x) for t in triples for x in t]
+        ijk = (ctypes.c_int * len(flat))(*flat)
+        out = (ctypes.c_double * (3 * len(triples)))()
+        p = make_problem_df_struct(prob)
+        _check(load_library().ccsdt_triple_energies_df(self._h, ctypes.byref(p), _prec(precision), len(triples),
+                                                        ijk, _stream(stream), out))
+        return [(out[3 * n], out[3 * n + 1], out[3 * n + 2]) for n in range(len(triples))]
 
     def energy_batched(self, probs: list, precision="fp32", stream=None):
         """[(E, E4, E5)] for many problems in one submission."""

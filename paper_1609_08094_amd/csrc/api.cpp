@@ -37,7 +37,7 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
-enum { K_PACK = 0, K_CONTRACT = 1, K_ENERGY = 2, K_REDUCE = 3, K_NCLASS = 4 };
+enum { K_PACK = 0, K_CONTRACT = 1, K_ENERGY = 2, K_REDUCE = 3, K_ASSEMBLE = 4, K_NCLASS = 5 };
 
 size_t env_size(const char* name, size_t dflt) {
     const char* s = std::getenv(name);
@@ -214,7 +214,7 @@ bool is_device_ptr(const void* p) {
     return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
-int check_problem(const ccsdt_problem* p, int idx) {
+int check_problem(const ccsdt_problem* p, int idx, bool need_vvvo = true) {
     const std::string where = idx >= 0 ? " (problem " + std::to_string(idx) + ")" : "";
     if (!p) return fail(CCSDT_EINVAL, "null problem" + where);
     if (p->nocc < 1 || p->nvirt < 1) return fail(CCSDT_EINVAL, "nocc and nvirt must be >= 1" + where);
@@ -223,6 +223,7 @@ int check_problem(const ccsdt_problem* p, int idx) {
     const double* ptrs[7] = {p->eps_o, p->eps_v, p->t1, p->t2, p->vvvo, p->ovoo, p->ovov};
     const char* names[7] = {"eps_o", "eps_v", "t1", "t2", "vvvo", "ovoo", "ovov"};
     for (int n = 0; n < 7; ++n) {
+        if (n == 4 && !need_vvvo) continue;
         if (!ptrs[n]) return fail(CCSDT_EINVAL, std::string("null pointer ") + names[n] + where);
         if (!is_device_ptr(ptrs[n]))
             return fail(CCSDT_EINVAL, std::string(names[n]) + " is not a device pointer" + where);
@@ -279,7 +280,10 @@ int tile_cfg_for(const ccsdt_context* ctx, int prec, int v) {
 }
 
 struct ProbLayout {
-    ccsdt_problem p;
+    ccsdt_problem p;          // p.vvvo is null when G's particle part is DF-assembled
+    const double* bvv;        // density-fitting factors (DF problems only)
+    const double* bvo;
+    int naux;
     int Kp;
     int cfg;
     size_t gc_off, tc_off;  // byte offsets in the pooled pack buffers
@@ -411,6 +415,8 @@ int enqueue_pipeline(ccsdt_context* ctx, const Plan& P, int prec, hipStream_t s,
     for (const auto& L : P.probs) {
         char* g = static_cast<char*>(ctx->gc.p) + L.gc_off;
         char* t = static_cast<char*>(ctx->tc.p) + L.tc_off;
+        if (L.bvv)
+            LAUNCH(K_ASSEMBLE, launch_assemble_df(prec, L.p.nocc, L.p.nvirt, L.naux, L.Kp, L.bvv, L.bvo, g, s));
         LAUNCH(K_PACK, launch_pack(prec, L.p.nocc, L.p.nvirt, L.Kp, L.p.vvvo, L.p.t2, L.p.ovoo, g, t, s));
     }
     const Slot* dslots = static_cast<const Slot*>(ctx->slots.p);
@@ -683,22 +689,11 @@ int ccsdt_profile_get(ccsdt_context* ctx, int cls, int64_t* launches, double* to
     return CCSDT_OK;
 }
 
-static int energy_many(ccsdt_context* ctx, int nprob, const ccsdt_problem* probs, int prec, void* stream,
-                       double* out_host) {
-    if (!ctx) return fail(CCSDT_EINVAL, "null context");
-    if (!out_host) return fail(CCSDT_EINVAL, "null output");
-    if (nprob < 1 || !probs) return fail(CCSDT_EINVAL, "no problems");
-    CHK(check_prec(prec));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int p = 0; p < nprob; ++p) CHK(check_problem(&probs[p], nprob > 1 ? p : -1));
-    if (nprob > 1 && !ctx->profile && env_int("CCSDT_GRAPH", 1) != 0)
-        return energy_graph(ctx, nprob, probs, prec, s, out_host);
-
-    prof_start_call(ctx);
-    for (int p = 0; p < nprob; ++p) CHK(check_gap(&probs[p], s, nprob > 1 ? p : -1));
-    Plan P;
-    std::vector<int> tb;
-    whole_problem_plan(P, nprob, probs, tb);
+// Eager E(T) of the problems in P (work list already built, trip_begin per
+// problem): pipeline, final reduce, copy of (E, E4, E5) rows to out_host.
+static int eager_energy(ccsdt_context* ctx, Plan& P, const std::vector<int>& tb, int prec, hipStream_t s,
+                        double* out_host) {
+    const int nprob = (int)P.probs.size();
     CHK(run_pipeline(ctx, P, prec, s, nullptr));
     CHK(ensure(ctx, ctx->tripbeg, sizeof(int) * (nprob + 1), "triple ranges"));
     CHK(ensure(ctx, ctx->out, sizeof(double) * 4 * nprob, "result"));
@@ -715,9 +710,62 @@ static int energy_many(ccsdt_context* ctx, int nprob, const ccsdt_problem* probs
     return CCSDT_OK;
 }
 
+static int energy_many(ccsdt_context* ctx, int nprob, const ccsdt_problem* probs, int prec, void* stream,
+                       double* out_host) {
+    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    if (!out_host) return fail(CCSDT_EINVAL, "null output");
+    if (nprob < 1 || !probs) return fail(CCSDT_EINVAL, "no problems");
+    CHK(check_prec(prec));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int p = 0; p < nprob; ++p) CHK(check_problem(&probs[p], nprob > 1 ? p : -1));
+    if (nprob > 1 && !ctx->profile && env_int("CCSDT_GRAPH", 1) != 0)
+        return energy_graph(ctx, nprob, probs, prec, s, out_host);
+
+    prof_start_call(ctx);
+    for (int p = 0; p < nprob; ++p) CHK(check_gap(&probs[p], s, nprob > 1 ? p : -1));
+    Plan P;
+    std::vector<int> tb;
+    whole_problem_plan(P, nprob, probs, tb);
+    return eager_energy(ctx, P, tb, prec, s, out_host);
+}
+
+// Validates a DF problem and turns it into the common problem description
+// (vvvo null) plus the factor pointers.
+static int df_layout(const ccsdt_problem_df* d, ProbLayout& L) {
+    if (!d) return fail(CCSDT_EINVAL, "null problem");
+    ccsdt_problem p{d->nocc, d->nvirt, d->eps_o, d->eps_v, d->t1, d->t2, nullptr, d->ovoo, d->ovov};
+    CHK(check_problem(&p, -1, false));
+    if (d->naux < 1 || d->naux > 65536) return fail(CCSDT_EINVAL, "naux must be in 1..65536");
+    if (!d->bvv || !d->bvo) return fail(CCSDT_EINVAL, "null pointer bvv or bvo");
+    if (!is_device_ptr(d->bvv) || !is_device_ptr(d->bvo)) return fail(CCSDT_EINVAL, "bvv or bvo is not a device pointer");
+    L = ProbLayout{};
+    L.p = p;
+    L.bvv = d->bvv;
+    L.bvo = d->bvo;
+    L.naux = d->naux;
+    return CCSDT_OK;
+}
+
 int ccsdt_energy(ccsdt_context* ctx, const ccsdt_problem* prob, int precision, void* hip_stream, double* out_host) {
     if (!prob) return fail(CCSDT_EINVAL, "null problem");
     return energy_many(ctx, 1, prob, precision, hip_stream, out_host);
+}
+
+int ccsdt_energy_df(ccsdt_context* ctx, const ccsdt_problem_df* prob, int precision, void* hip_stream,
+                    double* out_host) {
+    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    if (!out_host) return fail(CCSDT_EINVAL, "null output");
+    CHK(check_prec(precision));
+    ProbLayout L;
+    CHK(df_layout(prob, L));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    prof_start_call(ctx);
+    CHK(check_gap(&L.p, s, -1));
+    Plan P;
+    std::vector<int> tb;
+    whole_problem_plan(P, 1, &L.p, tb);
+    P.probs[0] = L;
+    return eager_energy(ctx, P, tb, precision, s, out_host);
 }
 
 int ccsdt_energy_batched(ccsdt_context* ctx, int nprob, const ccsdt_problem* probs_host, int precision,
@@ -741,14 +789,10 @@ int ccsdt_triples_energy(int nocc, int nvirt, const double* eps_o, const double*
     return CCSDT_OK;
 }
 
-int ccsdt_triple_energies(ccsdt_context* ctx, const ccsdt_problem* prob, int precision, int ntrip,
-                          const int* ijk_host, void* hip_stream, double* out_host) {
-    if (!ctx) return fail(CCSDT_EINVAL, "null context");
-    if (!out_host || !ijk_host) return fail(CCSDT_EINVAL, "null argument");
-    if (ntrip < 1) return fail(CCSDT_EINVAL, "ntrip must be >= 1");
-    CHK(check_prec(precision));
-    CHK(check_problem(prob, -1));
-    const int o = prob->nocc;
+// Per-triple energies of one validated problem layout.
+static int triple_energies_impl(ccsdt_context* ctx, const ProbLayout& L, int precision, int ntrip,
+                                const int* ijk_host, void* hip_stream, double* out_host) {
+    const int o = L.p.nocc;
     Plan P;
     std::vector<int> zero_rows;
     for (int t = 0; t < ntrip; ++t) {
@@ -761,9 +805,8 @@ int ccsdt_triple_energies(ccsdt_context* ctx, const ccsdt_problem* prob, int pre
     }
     prof_start_call(ctx);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    CHK(check_gap(prob, s, -1));
-    P.probs.assign(1, ProbLayout{});
-    P.probs[0].p = *prob;
+    CHK(check_gap(&L.p, s, -1));
+    P.probs.assign(1, L);
     P.n_out = (size_t)ntrip;
     CHK(run_pipeline(ctx, P, precision, s, nullptr));
     CHK(ensure_host((void**)&ctx->host_out, &ctx->host_out_bytes, sizeof(double) * 3 * ntrip));
@@ -773,6 +816,29 @@ int ccsdt_triple_energies(ccsdt_context* ctx, const ccsdt_problem* prob, int pre
     for (int t : zero_rows) ctx->host_out[3 * t] = ctx->host_out[3 * t + 1] = ctx->host_out[3 * t + 2] = 0.0;
     std::memcpy(out_host, ctx->host_out, sizeof(double) * 3 * ntrip);
     return CCSDT_OK;
+}
+
+int ccsdt_triple_energies(ccsdt_context* ctx, const ccsdt_problem* prob, int precision, int ntrip,
+                          const int* ijk_host, void* hip_stream, double* out_host) {
+    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    if (!out_host || !ijk_host) return fail(CCSDT_EINVAL, "null argument");
+    if (ntrip < 1) return fail(CCSDT_EINVAL, "ntrip must be >= 1");
+    CHK(check_prec(precision));
+    CHK(check_problem(prob, -1));
+    ProbLayout L{};
+    L.p = *prob;
+    return triple_energies_impl(ctx, L, precision, ntrip, ijk_host, hip_stream, out_host);
+}
+
+int ccsdt_triple_energies_df(ccsdt_context* ctx, const ccsdt_problem_df* prob, int precision, int ntrip,
+                             const int* ijk_host, void* hip_stream, double* out_host) {
+    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    if (!out_host || !ijk_host) return fail(CCSDT_EINVAL, "null argument");
+    if (ntrip < 1) return fail(CCSDT_EINVAL, "ntrip must be >= 1");
+    CHK(check_prec(precision));
+    ProbLayout L;
+    CHK(df_layout(prob, L));
+    return triple_energies_impl(ctx, L, precision, ntrip, ijk_host, hip_stream, out_host);
 }
 
 int ccsdt_debug_w(ccsdt_context* ctx, const ccsdt_problem* prob, int precision, int i, int j, int k,

@@ -55,8 +55,12 @@ struct Slot {
 
 // ---- launchers (defined in the .hip files) ---------------------------------
 // Pack one problem's operands into the precision's layout (see pack.hip).
+// With vvvo == nullptr the particle part of G is left to launch_assemble_df.
 hipError_t launch_pack(int prec, int o, int v, int Kp, const double* vvvo, const double* t2,
                        const double* ovoo, void* gc, void* tc, hipStream_t s);
+// Particle part of G from density-fitting factors (see df.hip).
+hipError_t launch_assemble_df(int prec, int o, int v, int naux, int Kp, const double* bvv, const double* bvo,
+                              void* gc, hipStream_t s);
 // Both contraction passes over the slots of a chunk (one launch).
 hipError_t launch_contract(int prec, int tile_cfg, const Slot* d_slots, int nslot, int total_wg, hipStream_t s);
 // Energy partials over the block orbits of every slot.

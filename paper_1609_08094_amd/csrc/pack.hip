@@ -19,101 +19,106 @@
 //   BF16X3 hi = bf16(x), lo = bf16(x - hi), stored in groups of eight
 //          elements as [hi x8][lo x8] (16 bf16 = 32 bytes per group), so that
 //          one 32-byte load gives a lane both halves of an MFMA fragment.
+#include <algorithm>
+
 #include "common.hpp"
+#include "pack_out.hpp"
 
 namespace ccsdt {
 
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// G particle part.  For fixed (y, d) the (x, p) plane of vvvo[y][d][x][p]
+// is one contiguous run of v*o doubles; with q = x*o + p, a workgroup takes
+// 64 values of d and 128 consecutive q, reads 64 runs of 1 KB, transposes
+// through LDS and writes, for each q, 64 consecutive kappa = d of row
+// G[p][x][y].  Grid: (q tiles) x (d tiles) x y, q tiles fastest.
+constexpr int PK_D = 64, PK_Q = 128;
 
-struct OutF64 {
-    using T = double;
-    static __device__ __forceinline__ int64_t rowlen(int Kp) { return Kp; }
-    static __device__ __forceinline__ void put(T* row, int kappa, double x) { row[kappa] = x; }
-};
-struct OutF32 {
-    using T = float;
-    static __device__ __forceinline__ int64_t rowlen(int Kp) { return Kp; }
-    static __device__ __forceinline__ void put(T* row, int kappa, double x) { row[kappa] = (float)x; }
-};
-struct OutB3 {
-    using T = uint16_t;
-    static __device__ __forceinline__ int64_t rowlen(int Kp) { return 2 * (int64_t)Kp; }
-    static __device__ __forceinline__ void put(T* row, int kappa, double x) {
-        uint16_t hi = bf16_rne((float)x);
-        float hf = __uint_as_float((uint32_t)hi << 16);
-        uint16_t lo = bf16_rne((float)(x - (double)hf));
-        int base = (kappa >> 3) * 16 + (kappa & 7);
-        row[base] = hi;
-        row[base + 8] = lo;
-    }
-};
-
-// G particle part: one workgroup per (y, x); tiles of 64 d x 32 p through LDS.
 template <class O>
 __global__ __launch_bounds__(256) void pack_g_particle(const double* __restrict__ vvvo, int o, int v,
                                                        int Kp, typename O::T* __restrict__ g) {
-    __shared__ double tile[64][33];
-    const int y = blockIdx.x / v;
-    const int x = blockIdx.x % v;
+    __shared__ double tile[PK_D][PK_Q + 1];
+    const int64_t nq = (int64_t)v * o;
+    const int qtiles = (int)((nq + PK_Q - 1) / PK_Q);
+    const int dtiles = (v + PK_D - 1) / PK_D;
+    const int64_t bid = blockIdx.x;
+    const int qt = (int)(bid % qtiles);
+    const int dt = (int)((bid / qtiles) % dtiles);
+    const int y = (int)(bid / ((int64_t)qtiles * dtiles));
+    const int64_t q0 = (int64_t)qt * PK_Q;
+    const int d0 = dt * PK_D;
+    const GLOBAL double* src = gp(vvvo);
+    for (int e = threadIdx.x; e < PK_D * PK_Q; e += 256) {
+        const int dd = e / PK_Q, qq = e % PK_Q;
+        const int d = d0 + dd;
+        const int64_t q = q0 + qq;
+        double val = 0.0;
+        if (d < v && q < nq) val = src[((int64_t)y * v + d) * nq + q];
+        tile[dd][qq] = val;
+    }
+    __syncthreads();
     const int64_t rl = O::rowlen(Kp);
-    for (int d0 = 0; d0 < v; d0 += 64) {
-        for (int p0 = 0; p0 < o; p0 += 32) {
-            __syncthreads();
-            for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-                int dd = e >> 5, pp = e & 31;
-                int d = d0 + dd, p = p0 + pp;
-                double val = 0.0;
-                if (d < v && p < o) val = vvvo[(((int64_t)y * v + d) * v + x) * o + p];
-                tile[dd][pp] = val;
-            }
-            __syncthreads();
-            for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-                int pp = e >> 6, dd = e & 63;
-                int d = d0 + dd, p = p0 + pp;
-                if (d < v && p < o) {
-                    typename O::T* row = g + (((int64_t)p * v + x) * v + y) * rl;
-                    O::put(row, d, tile[dd][pp]);
-                }
-            }
+    for (int e = threadIdx.x; e < PK_D * PK_Q; e += 256) {
+        const int qq = e / PK_D, dd = e % PK_D;
+        const int d = d0 + dd;
+        const int64_t q = q0 + qq;
+        if (d < v && q < nq) {
+            const int x = (int)(q / o), p = (int)(q % o);
+            typename O::T* row = g + (((int64_t)p * v + x) * v + y) * rl;
+            O::put(row, d, tile[dd][qq]);
         }
     }
 }
 
-// G hole part and zero padding: one workgroup per (p, x).
+// G hole part and zero padding: kappa = v + l of rows G[p][x][y] from
+// t2[p][l][x][y].  A workgroup takes (p, x) and 64 values of y; per chunk of
+// 64 values of kappa - v it reads the runs t2[p][l][x][y0..y0+63],
+// transposes through LDS, and writes for each y consecutive kappa (hole part,
+// then zeros up to Kp).
 template <class O>
 __global__ __launch_bounds__(256) void pack_g_hole(const double* __restrict__ t2, int o, int v, int Kp,
                                                    typename O::T* __restrict__ g) {
-    const int p = blockIdx.x / v;
-    const int x = blockIdx.x % v;
+    __shared__ double tile[64][65];
+    const int ytiles = (v + 63) / 64;
+    const int px = blockIdx.x / ytiles;
+    const int y0 = (blockIdx.x % ytiles) * 64;
+    const int p = px / v, x = px % v;
+    const int kext = Kp - v;
     const int64_t rl = O::rowlen(Kp);
     typename O::T* rows = g + ((int64_t)p * v + x) * v * rl;
-    const int kext = Kp - v;  // hole entries plus padding per row
-    for (int e = threadIdx.x; e < kext * v; e += 256) {
-        int l = e / v, y = e % v;
-        double val = 0.0;
-        if (l < o) val = t2[(((int64_t)p * o + l) * v + x) * v + y];
-        O::put(rows + (int64_t)y * rl, v + l, val);
+    for (int l0 = 0; l0 < kext; l0 += 64) {
+        const int lc = min(64, kext - l0);
+        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+            const int ll = e / 64, yy = e % 64;
+            const int l = l0 + ll;
+            double val = 0.0;
+            if (l < o && y0 + yy < v) val = t2[(((int64_t)p * o + l) * v + x) * v + y0 + yy];
+            tile[ll][yy] = val;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * lc; e += 256) {
+            const int yy = e / lc, ll = e % lc;
+            if (y0 + yy < v) O::put(rows + (int64_t)(y0 + yy) * rl, v + l0 + ll, tile[ll][yy]);
+        }
+        __syncthreads();
     }
 }
 
-// T rows: one workgroup per (r, q, z).
+// T rows: one workgroup per row (r, q, z), grid-stride over the o*o*v rows.
 template <class O>
 __global__ __launch_bounds__(256) void pack_t(const double* __restrict__ t2, const double* __restrict__ ovoo,
                                               int o, int v, int Kp, typename O::T* __restrict__ t) {
-    const int64_t row = blockIdx.x;
-    const int z = (int)(row % v);
-    const int rq = (int)(row / v);
-    const int r = rq / o, q = rq % o;
-    typename O::T* out = t + row * O::rowlen(Kp);
-    for (int kap = threadIdx.x; kap < Kp; kap += 256) {
-        double val = 0.0;
-        if (kap < v) val = t2[row * v + kap];
-        else if (kap < v + o) val = -ovoo[(((int64_t)r * v + z) * o + q) * o + (kap - v)];
-        O::put(out, kap, val);
+    const int64_t nrows = (int64_t)o * o * v;
+    for (int64_t row = blockIdx.x; row < nrows; row += gridDim.x) {
+        const int z = (int)(row % v);
+        const int rq = (int)(row / v);
+        const int r = rq / o, q = rq % o;
+        typename O::T* out = t + row * O::rowlen(Kp);
+        for (int kap = threadIdx.x; kap < Kp; kap += 256) {
+            double val = 0.0;
+            if (kap < v) val = t2[row * v + kap];
+            else if (kap < v + o) val = -ovoo[(((int64_t)r * v + z) * o + q) * o + (kap - v)];
+            O::put(out, kap, val);
+        }
     }
 }
 
@@ -122,13 +127,21 @@ static hipError_t pack_impl(int o, int v, int Kp, const double* vvvo, const doub
                             void* gc, void* tc, hipStream_t s) {
     auto* g = static_cast<typename O::T*>(gc);
     auto* t = static_cast<typename O::T*>(tc);
-    hipLaunchKernelGGL(pack_g_particle<O>, dim3((unsigned)v * v), dim3(256), 0, s, vvvo, o, v, Kp, g);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(pack_g_hole<O>, dim3((unsigned)o * v), dim3(256), 0, s, t2, o, v, Kp, g);
+    hipError_t e;
+    if (vvvo) {
+        const int64_t qtiles = ((int64_t)v * o + PK_Q - 1) / PK_Q, dtiles = (v + PK_D - 1) / PK_D;
+        hipLaunchKernelGGL(pack_g_particle<O>, dim3((unsigned)(qtiles * dtiles * v)), dim3(256), 0, s, vvvo, o, v,
+                           Kp, g);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(pack_g_hole<O>, dim3((unsigned)((int64_t)o * v * ((v + 63) / 64))), dim3(256), 0, s, t2, o,
+                       v, Kp, g);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(pack_t<O>, dim3((unsigned)((int64_t)o * o * v)), dim3(256), 0, s, t2, ovoo, o, v, Kp, t);
+    const int64_t trows = (int64_t)o * o * v;
+    hipLaunchKernelGGL(pack_t<O>, dim3((unsigned)std::min<int64_t>(trows, (int64_t)1 << 22)), dim3(256), 0, s, t2,
+                       ovoo, o, v, Kp, t);
     return hipGetLastError();
 }
 

@@ -79,14 +79,20 @@ def _mp2_doubles(ovov: np.ndarray, eps_o: np.ndarray, eps_v: np.ndarray) -> np.n
 
 
 def make_problem(o: int, v: int, seed: int = 0, naux: int | None = None,
-                 with_eri: bool = False) -> dict:
+                 with_eri: bool = False, with_df: bool = False) -> dict:
     """Host float64 problem.  ``with_eri`` also returns the full 8-fold
     symmetric ERI tensor ``eri`` (tiny sizes), from which every block is
-    sliced so the blocks agree with it bit for bit."""
+    sliced so the blocks agree with it bit for bit.  ``with_df`` also returns
+    the density-fitting factors with the auxiliary index fastest,
+    bvv[a][b][Q] = B^Q_ab and bvo[c][i][Q] = B^Q_ci, and ``naux``."""
     B, eps_o, eps_v, t1 = draw_factors(o, v, seed, naux)
     O = slice(0, o)
     V = slice(o, o + v)
     out = dict(nocc=o, nvirt=v, eps_o=eps_o, eps_v=eps_v, t1=np.ascontiguousarray(t1))
+    if with_df:
+        out["naux"] = B.shape[0]
+        out["bvv"] = np.ascontiguousarray(B[:, V, V].transpose(1, 2, 0))
+        out["bvo"] = np.ascontiguousarray(B[:, V, O].transpose(1, 2, 0))
     if with_eri:
         g = full_eri(B)
         ovov = np.ascontiguousarray(g[O, V, O, V])
@@ -128,22 +134,29 @@ def make_batch(seed: int = 0, nprob: int = BATCH_NPROB) -> list[dict]:
 
 
 FIELDS = ("eps_o", "eps_v", "t1", "t2", "vvvo", "ovoo", "ovov")
+DF_FIELDS = ("bvv", "bvo")
 
 
 def to_device(prob: dict, device="cuda"):
     """Copy the float64 arrays of a host problem into torch tensors."""
     import torch
     out = dict(nocc=prob["nocc"], nvirt=prob["nvirt"])
-    for f in FIELDS:
-        out[f] = torch.from_numpy(np.ascontiguousarray(prob[f])).to(device)
+    if "naux" in prob:
+        out["naux"] = prob["naux"]
+    for f in FIELDS + DF_FIELDS:
+        if f in prob:
+            out[f] = torch.from_numpy(np.ascontiguousarray(prob[f])).to(device)
     return out
 
 
 def make_problem_device(o: int, v: int, seed: int = 0, naux: int | None = None,
-                        device="cuda", row_chunk: int = 8192) -> dict:
+                        device="cuda", row_chunk: int = 8192, with_vvvo: bool = True,
+                        with_df: bool = False) -> dict:
     """Same recipe and the same random draws as ``make_problem`` (numpy
     PCG64 on the host), with the integral products formed in float64 on the
-    GPU, for workloads whose (vv|vo) block does not fit host memory."""
+    GPU, for workloads whose (vv|vo) block does not fit host memory.
+    ``with_df`` adds bvv, bvo and naux as in ``make_problem``;
+    ``with_vvvo=False`` skips the (vv|vo) block."""
     import torch
     B, eps_o, eps_v, t1 = draw_factors(o, v, seed, naux)
     naux = B.shape[0]
@@ -161,6 +174,13 @@ def make_problem_device(o: int, v: int, seed: int = 0, naux: int | None = None,
     den = (eps_o[:, None, None, None] + eps_o[None, :, None, None]
            - eps_v[None, None, :, None] - eps_v[None, None, None, :])
     t2 = (ovov.permute(0, 2, 1, 3) / den).contiguous()
+    out = dict(nocc=o, nvirt=v, eps_o=eps_o, eps_v=eps_v, t1=t1, t2=t2, ovoo=ovoo, ovov=ovov)
+    if with_df:
+        out["naux"] = naux
+        out["bvv"] = Bd[:, o:, o:].permute(1, 2, 0).contiguous()
+        out["bvo"] = Bd[:, o:, :o].permute(1, 2, 0).contiguous()
+    if not with_vvvo:
+        return out
     Bvv = Bd[:, o:, o:].reshape(naux, v * v)
     Bvo = Bd[:, o:, :o].reshape(naux, v * o).contiguous()
     del Bd
@@ -181,7 +201,7 @@ def make_problem_device(o: int, v: int, seed: int = 0, naux: int | None = None,
             sym = 0.5 * (vvvo[a0:a1, b0:b1] + vvvo[b0:b1, a0:a1].transpose(0, 1))
             vvvo[a0:a1, b0:b1] = sym
             vvvo[b0:b1, a0:a1] = sym.transpose(0, 1)
-    return dict(nocc=o, nvirt=v, eps_o=eps_o, eps_v=eps_v, t1=t1, t2=t2, vvvo=vvvo,
-                ovoo=ovoo, ovov=ovov)
+    out["vvvo"] = vvvo
+    return out
 
 
