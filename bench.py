@@ -51,6 +51,14 @@ class _SliceStore:
         return self.slices[p]
 
 
+def ctx_energy(ctx, dev, prec, stream):
+    return ctx.energy(dev, prec, stream)
+
+
+def ctx_energy_df(ctx, dev, prec, stream):
+    return ctx.energy_df(dev, prec, stream)
+
+
 def cpu_baseline(dev, sample):
     import numpy as np
     import oracle
@@ -61,10 +69,19 @@ def cpu_baseline(dev, sample):
         threads = os.cpu_count()
     host = {f: dev[f].cpu().numpy() for f in ("eps_o", "eps_v", "t1", "t2", "ovoo", "ovov")}
     ps = sorted({p for t in sample for p in t})
-    host["vvvo"] = _SliceStore({p: np.ascontiguousarray(dev["vvvo"][..., p].cpu().numpy()) for p in ps})
     o, v = dev["nocc"], dev["nvirt"]
-    res = []
     t0 = time.perf_counter()
+    if "vvvo" in dev:
+        host["vvvo"] = _SliceStore({p: np.ascontiguousarray(dev["vvvo"][..., p].cpu().numpy()) for p in ps})
+        t0 = time.perf_counter()
+    else:
+        # density-fitted input: the oracle assembles the needed (vv|vo) slices
+        # itself (timed as part of the baseline)
+        bvv, bvo = dev["bvv"].cpu().numpy(), dev["bvo"].cpu().numpy()
+        t0 = time.perf_counter()
+        host["vvvo"] = _SliceStore({p: oracle.vvvo_from_df(bvv, np.ascontiguousarray(bvo[:, p:p + 1, :]))[..., 0]
+                                    for p in ps})
+    res = []
     for t in sample:
         res.append(oracle.triple_restricted(*t, host["eps_o"], host["eps_v"], host["t1"], host["t2"],
                                             host["vvvo"], host["ovoo"], host["ovov"]))
@@ -81,10 +98,14 @@ def main():
                     help="untimed full steps before the timed ones (an untimed prime pass over "
                          "four triples always runs first: it allocates every workspace buffer at "
                          "full size and loads the kernels)")
-    ap.add_argument("--config", default="C3", choices=["C0", "C1", "C2", "C3", "batch"],
-                    help="C0..C3: one problem of the named size; batch: 64 uneven problems "
-                         "(o ~ U{4..16}, v ~ U{40..160}) per step through one captured graph")
+    ap.add_argument("--config", default="C3", choices=["C0", "C1", "C2", "C3", "batch", "M0", "M1"],
+                    help="C0..C3: one (T) problem of the named size; batch: 64 uneven (T) problems "
+                         "(o ~ U{4..16}, v ~ U{40..160}) per step through one captured graph; "
+                         "M0, M1: RI-MP2 energy (M1: o=119, v=2546, naux=5852)")
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--input", default="eri", choices=["eri", "df"],
+                    help="eri: the (vv|vo) block is an input; df: density-fitting factors are the input and "
+                         "the library assembles the (vv|vo) operand on the GPU")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample", default="0,1,2",
@@ -101,11 +122,15 @@ def main():
 
     if args.config == "batch":
         return bench_batch(args, torch, ccsdt, synth)
+    if args.config in synth.MP2_CONFIGS:
+        return bench_mp2(args, torch, ccsdt, synth)
     cfg = synth.CONFIGS[args.config]
     o, v = cfg["o"], cfg["v"]
     log(f"bench: generating {args.config} o={o} v={v} seed={args.seed}")
     t0 = time.perf_counter()
-    dev = synth.make_problem_device(o, v, seed=args.seed, device="cuda")
+    df = args.input == "df"
+    dev = synth.make_problem_device(o, v, seed=args.seed, device="cuda", with_vvvo=not df, with_df=df)
+    energy = ctx_energy_df if df else ctx_energy
     torch.cuda.synchronize()
     log(f"bench: inputs ready in {time.perf_counter() - t0:.1f}s")
 
@@ -114,16 +139,17 @@ def main():
     ctx.profile(True)
     stream = torch.cuda.current_stream()
     log("bench: prime pass (allocation, kernel load)")
-    ctx.triple_energies(dev, [(0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)], args.precision, stream)
+    triples = ctx.triple_energies_df if df else ctx.triple_energies
+    triples(dev, [(0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)], args.precision, stream)
     for w in range(args.warmup):
         log(f"bench: warmup {w}")
-        ctx.energy(dev, args.precision, stream)
+        energy(ctx, dev, args.precision, stream)
     ctx.profile_reset()
     torch.cuda.synchronize()
     log(f"bench: timing {args.steps} step(s)")
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        E, E4, E5 = ctx.energy(dev, args.precision, stream)
+        E, E4, E5 = energy(ctx, dev, args.precision, stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
@@ -144,8 +170,8 @@ def main():
     cpu = None
     if sample:
         log(f"bench: sampled parity on {sample}")
-        gpu_s = ctx.triple_energies(dev, sample, args.precision, stream)
-        gpu_64 = ctx.triple_energies(dev, sample, "fp64", stream)
+        gpu_s = triples(dev, sample, args.precision, stream)
+        gpu_64 = triples(dev, sample, "fp64", stream)
         parity = {"triples": [list(t) for t in sample],
                   "e_gpu": [g[0] for g in gpu_s], "e_gpu_fp64": [g[0] for g in gpu_64]}
         if not args.no_cpu_baseline:
@@ -166,7 +192,9 @@ def main():
         "ms_per_step": ms, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
         "dtype": args.precision, "data": "synthetic (density-fitted integrals, MP2 doubles; seeded)",
         "config": {"workload": f"closed-shell (T) {args.config}: o={o} v={v} naux={3 * (o + v)} "
-                               f"seed={args.seed}, {args.precision}",
+                               f"seed={args.seed}, {args.precision}"
+                               + (", density-fitted (vv|vo) assembled on the GPU" if df else ""),
+                   "input": args.input,
                    "nocc": o, "nvirt": v, "precision": args.precision, "algorithmic_flops": F},
         "energy": {"E": E, "E4": E4, "E5": E5},
         "mfma_util": achieved / peak,
@@ -179,6 +207,96 @@ def main():
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def bench_mp2(args, torch, ccsdt, synth):
+    """RI-MP2 energy: one step = pack, every pair product and pair energy, and
+    the final sum.  roofline: the pair-product kernel, 2 v^2 naux flops per
+    pair (x3 MFMA flops for BF16X3)."""
+    cfg = synth.MP2_CONFIGS[args.config]
+    o, v, naux = cfg["o"], cfg["v"], cfg["naux"]
+    log(f"bench: generating RI-MP2 {args.config} o={o} v={v} naux={naux}")
+    t0 = time.perf_counter()
+    dev = synth.make_mp2_problem(o, v, naux, seed=args.seed, device="cuda")
+    torch.cuda.synchronize()
+    log(f"bench: inputs ready in {time.perf_counter() - t0:.1f}s")
+    F = ccsdt.rimp2_flops(o, v, naux)
+    ctx = ccsdt.Context()
+    ctx.profile(True)
+    stream = torch.cuda.current_stream()
+    # prime: a full chunk of pairs sizes every workspace buffer and loads the kernels
+    prime = [(i, j) for i in range(o) for j in range(i, o)][:256]
+    ctx.rimp2_pair_energies(dev, prime, args.precision, stream)
+    for w in range(args.warmup):
+        ctx.rimp2_energy(dev, args.precision, stream)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        E = ctx.rimp2_energy(dev, args.precision, stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    prof = {name: ctx.profile_get(name) for name in ccsdt.KERNEL_CLASSES}
+    ng, msg = prof["mp2_gemm"]
+    avg = msg / max(ng, 1)
+    achieved = MFMA_FACTOR[args.precision] * (F * args.steps / max(ng, 1)) / (avg * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    sample = [(0, 1), (o // 2, o - 1)]
+    g_s = ctx.rimp2_pair_energies(dev, sample, args.precision, stream)
+    g_64 = ctx.rimp2_pair_energies(dev, sample, "fp64", stream)
+    parity = {"pairs": [list(t) for t in sample], "e_gpu": g_s, "e_gpu_fp64": g_64}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import numpy as np
+        import oracle
+        eo, ev = dev["eps_o"].cpu().numpy(), dev["eps_v"].cpu().numpy()
+        rows = {i: dev["c_ov"][i].cpu().numpy() for t in sample for i in t}
+        c_host = _RowStore(rows)
+        t0 = time.perf_counter()
+        res = [oracle.rimp2_pair_energy(i, j, eo, ev, c_host) for i, j in sample]
+        dt = time.perf_counter() - t0
+        parity["e_oracle"] = res
+        parity["max_rel_gpu_vs_oracle"] = max(abs(a - b) / abs(b) for a, b in zip(g_s, res))
+        parity["max_rel_gpu_fp64_vs_oracle"] = max(abs(a - b) / abs(b) for a, b in zip(g_64, res))
+        fl = len(sample) * 2.0 * v * v * naux
+        cpu = {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": _threads(), "kind": "oracle",
+               "sample": f"{len(sample)} pair energies {sample} of RI-MP2 {args.config}, {fl:.3e} flops "
+                         f"(pair products counted once) in {dt:.1f}s"}
+    kernels = {k: {"launches": n // max(args.steps, 1), "ms_per_step": t / args.steps} for k, (n, t) in prof.items()}
+    line = {
+        "metric": "RI-MP2 GFLOP/s & MFMA util (pair products o(o+1)/2 * 2 v^2 naux)",
+        "value": F / (ms * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": args.precision,
+        "data": "synthetic (fitting coefficients N(0, 0.1^2); seeded)",
+        "config": {"workload": f"RI-MP2 {args.config}: o={o} v={v} naux={naux} seed={args.seed}, {args.precision}",
+                   "algorithmic_flops": F},
+        "energy": {"E_MP2": E},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None, "kernel": "mp2_gemm", "avg_launch_ms": avg,
+                     "launches_per_step": ng // args.steps},
+        "kernels": kernels, "parity_sample": parity, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+class _RowStore:
+    """c_ov stand-in for the oracle: serves the rows c_ov[i] of the sampled i."""
+
+    def __init__(self, rows):
+        self.rows = rows
+
+    def __getitem__(self, i):
+        return self.rows[i]
+
+
+def _threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        return os.cpu_count()
 
 
 def bench_batch(args, torch, ccsdt, synth):

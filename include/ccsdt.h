@@ -173,6 +173,37 @@ int ccsdt_triple_energies_df(ccsdt_context* ctx, const ccsdt_problem_df* prob, i
                              int ntrip, const int* ijk_host, void* hip_stream,
                              double* out_host);
 
+/* ---- RI-MP2 (the paper's second kernel) --------------------------------
+ * Closed-shell RI-MP2 correlation energy (Sec. 2.1, eq. mp2_energy with the
+ * denominators of eq. e_orb_diff and the integrals of eq. eri_sym_decomp):
+ *   E = - sum_ij sum_ab g_aibj (2 g_aibj - g_ajbi) / (e_a + e_b - e_i - e_j),
+ *   g_aibj = sum_Q C^Q_ai C^Q_bj.
+ * Input c_ov[i][a][Q] = C^Q_ai (o*v*naux float64, device, Q fastest): the
+ * fitting coefficients of eq. fitting_coef, computed by the caller.
+ * For each pair i <= j the library forms G_ij[a][b] = g_aibj as one matrix
+ * product over Q (precision as for (T): FP64, FP32 or BF16X3 products; the
+ * denominators and every sum in FP64) and E = sum_i e_ii + 2 sum_{i<j} e_ij.
+ * Limits: nocc <= 1024, nvirt <= 8192, naux <= 65536; CCSDT_EDENOM unless
+ * max(eps_o) < min(eps_v). */
+typedef struct ccsdt_mp2_problem {
+    int nocc;
+    int nvirt;
+    int naux;
+    const double* eps_o;
+    const double* eps_v;
+    const double* c_ov;
+} ccsdt_mp2_problem;
+
+/* *e_out = E_MP2 (Hartree). */
+int ccsdt_rimp2_energy(ccsdt_context* ctx, const ccsdt_mp2_problem* prob, int precision,
+                       void* hip_stream, double* e_out);
+/* Pair energies e_ij = - sum_ab g_aibj (2 g_aibj - g_ajbi) / D for the npair
+ * pairs ij_host[2*p], ij_host[2*p+1] (0 <= i <= j < nocc); out_host[npair]. */
+int ccsdt_rimp2_pair_energies(ccsdt_context* ctx, const ccsdt_mp2_problem* prob, int precision,
+                              int npair, const int* ij_host, void* hip_stream, double* out_host);
+/* Flops of the pair products: o(o+1)/2 * 2 v^2 naux. */
+double ccsdt_rimp2_flops(int nocc, int nvirt, int naux);
+
 /* Tile plans.  The contraction kernel has NTILE = 12 tile configurations
  * (workgroup tile shape, operand staging through registers or LDS, direct
  * global-to-LDS loads, one or two batch indices per workgroup, fragment
@@ -208,7 +239,7 @@ int ccsdt_graph_stats(ccsdt_context* ctx, int64_t* captures, int64_t* replays);
  * number of launches and their summed duration (ms) since the last reset.
  * Classes: 0 pack, 1 contraction (both passes: the six permutation terms of
  * W for every triple of a chunk), 2 energy, 3 reductions, 4 DF assembly of
- * the (vv|vo) operand. */
+ * the (vv|vo) operand, 5 RI-MP2 pair products, 6 RI-MP2 pair energies. */
 int ccsdt_profile_enable(ccsdt_context* ctx, int on);
 int ccsdt_profile_get(ccsdt_context* ctx, int kernel_class, int64_t* launches,
                       double* total_ms);

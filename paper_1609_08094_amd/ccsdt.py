@@ -17,13 +17,14 @@ FP64, FP32, BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 STATUS = {0: "CCSDT_OK", -1: "CCSDT_EINVAL", -2: "CCSDT_ENOMEM", -3: "CCSDT_EHIP",
           -4: "CCSDT_EUNSUPPORTED", -5: "CCSDT_EDENOM"}
-KERNEL_CLASSES = {"pack": 0, "contract": 1, "energy": 2, "reduce": 3, "assemble": 4}
+KERNEL_CLASSES = {"pack": 0, "contract": 1, "energy": 2, "reduce": 3, "assemble": 4, "mp2_gemm": 5,
+                  "mp2_energy": 6}
 FIELDS = ("eps_o", "eps_v", "t1", "t2", "vvvo", "ovoo", "ovov")
 EXPORTS = ("ccsdt_context_create", "ccsdt_context_destroy", "ccsdt_energy", "ccsdt_triples_energy",
            "ccsdt_triple_energies", "ccsdt_debug_w", "ccsdt_energy_batched", "ccsdt_profile_enable",
            "ccsdt_profile_get", "ccsdt_profile_reset", "ccsdt_flops", "ccsdt_last_error", "ccsdt_autotune",
            "ccsdt_plan_get", "ccsdt_plan_set", "ccsdt_graph_stats", "ccsdt_energy_df",
-           "ccsdt_triple_energies_df")
+           "ccsdt_triple_energies_df", "ccsdt_rimp2_energy", "ccsdt_rimp2_pair_energies", "ccsdt_rimp2_flops")
 DF_FIELDS = ("eps_o", "eps_v", "t1", "t2", "bvv", "bvo", "ovoo", "ovov")
 NTILE_CFG = 12
 
@@ -42,6 +43,11 @@ class Problem(ctypes.Structure):
 class ProblemDF(ctypes.Structure):
     _fields_ = [("nocc", ctypes.c_int), ("nvirt", ctypes.c_int), ("naux", ctypes.c_int)] + \
                [(f, ctypes.c_void_p) for f in DF_FIELDS]
+
+
+class MP2Problem(ctypes.Structure):
+    _fields_ = [("nocc", ctypes.c_int), ("nvirt", ctypes.c_int), ("naux", ctypes.c_int),
+                ("eps_o", ctypes.c_void_p), ("eps_v", ctypes.c_void_p), ("c_ov", ctypes.c_void_p)]
 
 
 _lib = None
@@ -70,6 +76,11 @@ def load_library(path: str = LIB_PATH):
     PD = ctypes.POINTER(ProblemDF)
     lib.ccsdt_energy_df.argtypes = [vp, PD, ip, vp, dp]
     lib.ccsdt_triple_energies_df.argtypes = [vp, PD, ip, ip, ctypes.POINTER(ctypes.c_int), vp, dp]
+    PM = ctypes.POINTER(MP2Problem)
+    lib.ccsdt_rimp2_energy.argtypes = [vp, PM, ip, vp, dp]
+    lib.ccsdt_rimp2_pair_energies.argtypes = [vp, PM, ip, ip, ctypes.POINTER(ctypes.c_int), vp, dp]
+    lib.ccsdt_rimp2_flops.argtypes = [ip, ip, ip]
+    lib.ccsdt_rimp2_flops.restype = ctypes.c_double
     lib.ccsdt_autotune.argtypes = [vp, P, ip, vp, ctypes.POINTER(ip)]
     lib.ccsdt_plan_get.argtypes = [vp, ip, ip, ctypes.POINTER(ip)]
     lib.ccsdt_plan_set.argtypes = [vp, ip, ip, ip]
@@ -78,7 +89,7 @@ def load_library(path: str = LIB_PATH):
     lib.ccsdt_flops.restype = ctypes.c_double
     lib.ccsdt_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("ccsdt_flops", "ccsdt_last_error"):
+        if name not in ("ccsdt_flops", "ccsdt_last_error", "ccsdt_rimp2_flops"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -123,6 +134,16 @@ def make_problem_df_struct(prob: dict) -> ProblemDF:
 
 def flops(nocc: int, nvirt: int) -> float:
     return load_library().ccsdt_flops(nocc, nvirt)
+
+
+def rimp2_flops(nocc: int, nvirt: int, naux: int) -> float:
+    return load_library().ccsdt_rimp2_flops(nocc, nvirt, naux)
+
+
+def make_mp2_struct(prob: dict) -> MP2Problem:
+    """MP2Problem struct (c_ov[i][a][Q]) from device tensors."""
+    vals = _dev_ptrs(prob, ("eps_o", "eps_v", "c_ov"))
+    return MP2Problem(int(prob["nocc"]), int(prob["nvirt"]), int(prob["naux"]), *vals)
 
 
 class Context:
@@ -175,6 +196,24 @@ class Context:
         _check(load_library().ccsdt_triple_energies_df(self._h, ctypes.byref(p), _prec(precision), len(triples),
                                                         ijk, _stream(stream), out))
         return [(out[3 * n], out[3 * n + 1], out[3 * n + 2]) for n in range(len(triples))]
+
+    def rimp2_energy(self, prob: dict, precision="fp32", stream=None) -> float:
+        """RI-MP2 correlation energy of {nocc, nvirt, naux, eps_o, eps_v, c_ov}."""
+        p = make_mp2_struct(prob)
+        e = ctypes.c_double()
+        _check(load_library().ccsdt_rimp2_energy(self._h, ctypes.byref(p), _prec(precision), _stream(stream),
+                                                  ctypes.byref(e)))
+        return e.value
+
+    def rimp2_pair_energies(self, prob: dict, pairs, precision="fp32", stream=None):
+        """[e_ij] for pairs (i, j), i <= j."""
+        flat = [int(x) for t in pairs for x in t]
+        ij = (ctypes.c_int * len(flat))(*flat)
+        out = (ctypes.c_double * len(pairs))()
+        p = make_mp2_struct(prob)
+        _check(load_library().ccsdt_rimp2_pair_energies(self._h, ctypes.byref(p), _prec(precision), len(pairs), ij,
+                                                         _stream(stream), out))
+        return list(out)
 
     def energy_batched(self, probs: list, precision="fp32", stream=None):
         """[(E, E4, E5)] for many problems in one submission."""

@@ -37,7 +37,8 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
-enum { K_PACK = 0, K_CONTRACT = 1, K_ENERGY = 2, K_REDUCE = 3, K_ASSEMBLE = 4, K_NCLASS = 5 };
+enum { K_PACK = 0, K_CONTRACT = 1, K_ENERGY = 2, K_REDUCE = 3, K_ASSEMBLE = 4, K_MP2_GEMM = 5, K_MP2_ENERGY = 6,
+       K_NCLASS = 7 };
 
 size_t env_size(const char* name, size_t dflt) {
     const char* s = std::getenv(name);
@@ -936,6 +937,119 @@ int ccsdt_graph_stats(ccsdt_context* ctx, int64_t* captures, int64_t* replays) {
     *captures = ctx->n_captures;
     *replays = ctx->n_replays;
     return CCSDT_OK;
+}
+
+// ---- RI-MP2 -----------------------------------------------------------------------
+// Workspace reuse: gc = packed coefficients, w = G_ij pair buffer, part =
+// energy partials, slots = pair table (int2) followed by pair indices (int),
+// etrip = pair energies, out = result.
+static int mp2_check(const ccsdt_mp2_problem* p) {
+    if (!p) return fail(CCSDT_EINVAL, "null problem");
+    if (p->nocc < 1 || p->nvirt < 1 || p->naux < 1) return fail(CCSDT_EINVAL, "nocc, nvirt and naux must be >= 1");
+    if (p->nocc > 1024 || p->nvirt > 8192 || p->naux > 65536)
+        return fail(CCSDT_EINVAL, "nocc > 1024, nvirt > 8192 or naux > 65536");
+    const double* ptrs[3] = {p->eps_o, p->eps_v, p->c_ov};
+    const char* names[3] = {"eps_o", "eps_v", "c_ov"};
+    for (int n = 0; n < 3; ++n) {
+        if (!ptrs[n]) return fail(CCSDT_EINVAL, std::string("null pointer ") + names[n]);
+        if (!is_device_ptr(ptrs[n])) return fail(CCSDT_EINVAL, std::string(names[n]) + " is not a device pointer");
+    }
+    return CCSDT_OK;
+}
+
+// Runs the pairs (i <= j) in ``pairs``; pair p's energy e_ij lands in
+// etrip[p]; with ``total`` the weighted sum lands in out[0].
+static int mp2_run(ccsdt_context* ctx, const ccsdt_mp2_problem* p, int prec, const std::vector<int2>& pairs,
+                   bool total, hipStream_t s) {
+    const int o = p->nocc, v = p->nvirt, naux = p->naux;
+    const int Kq = round_up(naux, KPAD);
+    const size_t es = elem_bytes(prec), wb = w_bytes(prec);
+    const size_t np = pairs.size();
+    const size_t per_slot = (size_t)v * v * wb;
+    const size_t nc = std::max<size_t>(1, std::min(np, ctx->w_budget / per_slot));
+    const int te = (v + 63) / 64;
+    const size_t npt = (size_t)te * (te + 1) / 2;
+    CHK(ensure(ctx, ctx->gc, (size_t)o * v * Kq * es, "packed coefficients"));
+    CHK(ensure(ctx, ctx->w, nc * per_slot, "pair buffer"));
+    CHK(ensure(ctx, ctx->part, nc * npt * sizeof(double), "energy partials"));
+    const size_t tab = np * sizeof(int2) + np * sizeof(int);
+    CHK(ensure(ctx, ctx->slots, tab, "pair table"));
+    CHK(ensure(ctx, ctx->etrip, np * sizeof(double), "pair energies"));
+    CHK(ensure(ctx, ctx->out, 4 * sizeof(double), "result"));
+    CHK(ensure_host((void**)&ctx->host_slots, &ctx->host_slots_bytes, tab));
+    char* h = reinterpret_cast<char*>(ctx->host_slots);
+    std::memcpy(h, pairs.data(), np * sizeof(int2));
+    int* hidx = reinterpret_cast<int*>(h + np * sizeof(int2));
+    for (size_t q = 0; q < np; ++q) hidx[q] = (int)q;
+    HIPCHK(hipMemcpyAsync(ctx->slots.p, h, tab, hipMemcpyHostToDevice, s));
+    const int2* dpairs = static_cast<const int2*>(ctx->slots.p);
+    const int* didx = reinterpret_cast<const int*>(static_cast<char*>(ctx->slots.p) + np * sizeof(int2));
+    LAUNCH(K_PACK, launch_mp2_pack(prec, o, v, naux, Kq, p->c_ov, ctx->gc.p, s));
+    for (size_t c0 = 0; c0 < np; c0 += nc) {
+        const int n = (int)std::min(nc, np - c0);
+        LAUNCH(K_MP2_GEMM, launch_mp2_gemm(prec, ctx->gc.p, dpairs + c0, n, v, Kq, ctx->w.p, s));
+        LAUNCH(K_MP2_ENERGY, launch_mp2_energy(prec, ctx->w.p, dpairs + c0, n, p->eps_o, p->eps_v, v,
+                                               static_cast<double*>(ctx->part.p), didx + c0,
+                                               static_cast<double*>(ctx->etrip.p), s));
+    }
+    if (total)
+        LAUNCH(K_REDUCE, launch_mp2_final(static_cast<const double*>(ctx->etrip.p), dpairs, (int)np,
+                                          static_cast<double*>(ctx->out.p), s));
+    return CCSDT_OK;
+}
+
+int ccsdt_rimp2_energy(ccsdt_context* ctx, const ccsdt_mp2_problem* prob, int precision, void* hip_stream,
+                       double* e_out) {
+    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    if (!e_out) return fail(CCSDT_EINVAL, "null output");
+    CHK(check_prec(precision));
+    CHK(mp2_check(prob));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    prof_start_call(ctx);
+    ccsdt_problem q{prob->nocc, prob->nvirt, prob->eps_o, prob->eps_v, nullptr, nullptr, nullptr, nullptr, nullptr};
+    CHK(check_gap(&q, s, -1));
+    std::vector<int2> pairs;
+    for (int i = 0; i < prob->nocc; ++i)
+        for (int j = i; j < prob->nocc; ++j) pairs.push_back(make_int2(i, j));
+    CHK(mp2_run(ctx, prob, precision, pairs, true, s));
+    CHK(ensure_host((void**)&ctx->host_out, &ctx->host_out_bytes, sizeof(double)));
+    HIPCHK(hipMemcpyAsync(ctx->host_out, ctx->out.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    CHK(prof_collect(ctx));
+    *e_out = ctx->host_out[0];
+    return CCSDT_OK;
+}
+
+int ccsdt_rimp2_pair_energies(ccsdt_context* ctx, const ccsdt_mp2_problem* prob, int precision, int npair,
+                              const int* ij_host, void* hip_stream, double* out_host) {
+    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    if (!out_host || !ij_host) return fail(CCSDT_EINVAL, "null argument");
+    if (npair < 1) return fail(CCSDT_EINVAL, "npair must be >= 1");
+    CHK(check_prec(precision));
+    CHK(mp2_check(prob));
+    std::vector<int2> pairs;
+    for (int q = 0; q < npair; ++q) {
+        const int i = ij_host[2 * q], j = ij_host[2 * q + 1];
+        if (!(0 <= i && i <= j && j < prob->nocc))
+            return fail(CCSDT_EINVAL, "pair " + std::to_string(q) + " is not 0 <= i <= j < nocc");
+        pairs.push_back(make_int2(i, j));
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    prof_start_call(ctx);
+    ccsdt_problem q{prob->nocc, prob->nvirt, prob->eps_o, prob->eps_v, nullptr, nullptr, nullptr, nullptr, nullptr};
+    CHK(check_gap(&q, s, -1));
+    CHK(mp2_run(ctx, prob, precision, pairs, false, s));
+    CHK(ensure_host((void**)&ctx->host_out, &ctx->host_out_bytes, sizeof(double) * npair));
+    HIPCHK(hipMemcpyAsync(ctx->host_out, ctx->etrip.p, sizeof(double) * npair, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    CHK(prof_collect(ctx));
+    std::memcpy(out_host, ctx->host_out, sizeof(double) * npair);
+    return CCSDT_OK;
+}
+
+double ccsdt_rimp2_flops(int nocc, int nvirt, int naux) {
+    const double o = nocc, v = nvirt, q = naux;
+    return o * (o + 1) / 2 * 2.0 * v * v * q;
 }
 
 }  // extern "C"

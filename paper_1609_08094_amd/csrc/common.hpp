@@ -75,6 +75,17 @@ hipError_t launch_final_reduce(const int* d_trip_begin, int nprob, const double*
 // W (any precision, blocked layout) of one slot as dense float64 [a][b][c].
 hipError_t launch_widen_w(int prec, const void* w, int v, double* out, hipStream_t s);
 
+// RI-MP2 (see mp2.hip).  Pack c_ov rows into Kq-long packed rows; G_ij for
+// the nslot pairs d_pairs[0..nslot) into gbuf (v*v per slot); per-slot
+// energies into e_pair[d_pair_index[s]]; the weighted final sum into out[0].
+hipError_t launch_mp2_pack(int prec, int o, int v, int naux, int Kq, const double* c_ov, void* cpk, hipStream_t s);
+hipError_t launch_mp2_gemm(int prec, const void* cpk, const int2* d_pairs, int nslot, int v, int Kq, void* gbuf,
+                           hipStream_t s);
+hipError_t launch_mp2_energy(int prec, const void* gbuf, const int2* d_pairs, int nslot, const double* eps_o,
+                             const double* eps_v, int v, double* partials, const int* d_pair_index, double* e_pair,
+                             hipStream_t s);
+hipError_t launch_mp2_final(const double* e_pair, const int2* d_all_pairs, int npairs, double* out, hipStream_t s);
+
 // Orbital energies of one problem, for the denominator sign check.
 struct GapDesc {
     const double* eps_o;

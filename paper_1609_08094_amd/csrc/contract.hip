@@ -25,98 +25,9 @@
 // Within a chunk each lane owns a contiguous run of k; A and B use the same
 // assignment, so the dot product covers every k exactly once.
 #include "common.hpp"
+#include "mfma.hpp"
 
 namespace ccsdt {
-
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // HIP uint4 blocks scalar replacement
-
-// Workgroups are dispatched round-robin over the XCDs; give each XCD a
-// contiguous range of logical work so tiles sharing operand rows share an L2.
-__device__ __forceinline__ int xcd_remap(int bid, int total) {
-    const int q = total / NXCD, r = total % NXCD;
-    const int x = bid % NXCD, idx = bid / NXCD;
-    return x * q + min(x, r) + idx;
-}
-
-struct PrecF64 {
-    using E = double;
-    using W = double;
-    using Acc = f64x4;
-    static constexpr int KCH = 16;
-    static constexpr int UNITS = 1;
-    struct Frag { f64x4 x; };
-    static __device__ __forceinline__ int out_row(int lane, int r) { return (lane >> 4) + 4 * r; }
-    static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
-        f.x = *reinterpret_cast<const GLOBAL f64x4*>(gp(row + c * 16 + 4 * (lane >> 4)));
-    }
-    // LDS staging (128-byte rows of eight 16-byte chunks, see contract_lds_kernel).
-    static constexpr int NSUB = 1;     // k sub-steps per 128-byte LDS row chunk set
-    static constexpr bool SPLIT = true;  // a lane's 32 bytes live in LDS chunks g and 4 + g
-    static __device__ __forceinline__ void load_lds(Frag& f, const char* row, int g, int sub, int sw) {
-        const double2 x0 = *reinterpret_cast<const double2*>(row + 16 * (g ^ sw));
-        const double2 x1 = *reinterpret_cast<const double2*>(row + 16 * ((4 + g) ^ sw));
-        f.x = f64x4{x0.x, x0.y, x1.x, x1.y};
-    }
-    static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[0], b.x[0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[1], b.x[1], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[2], b.x[2], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[3], b.x[3], acc, 0, 0, 0);
-    }
-};
-
-struct PrecF32 {
-    using E = float;
-    using W = float;
-    using Acc = f32x4;
-    static constexpr int KCH = 16;
-    static constexpr int UNITS = 1;
-    struct Frag { f32x4 x; };
-    static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
-    static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
-        f.x = *reinterpret_cast<const GLOBAL f32x4*>(gp(row + c * 16 + 4 * (lane >> 4)));
-    }
-    static constexpr int NSUB = 2;
-    static constexpr bool SPLIT = false;  // sub-step s, lane group g reads LDS chunk 4 s + g
-    static __device__ __forceinline__ void load_lds(Frag& f, const char* row, int g, int sub, int sw) {
-        f.x = *reinterpret_cast<const f32x4*>(row + 16 * ((4 * sub + g) ^ sw));
-    }
-    static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[0], b.x[0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[1], b.x[1], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[2], b.x[2], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[3], b.x[3], acc, 0, 0, 0);
-    }
-};
-
-struct PrecB3 {
-    using E = uint16_t;
-    using W = float;
-    using Acc = f32x4;
-    static constexpr int KCH = 32;
-    static constexpr int UNITS = 2;
-    struct Frag { bf16x8 hi, lo; };
-    static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
-    static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
-        const GLOBAL E* p = gp(row + (c * 4 + (lane >> 4)) * 16);
-        f.hi = *reinterpret_cast<const GLOBAL bf16x8*>(p);
-        f.lo = *reinterpret_cast<const GLOBAL bf16x8*>(p + 8);
-    }
-    static constexpr int NSUB = 1;
-    static constexpr bool SPLIT = true;  // hi of group g in LDS chunk g, lo in chunk 4 + g
-    static __device__ __forceinline__ void load_lds(Frag& f, const char* row, int g, int sub, int sw) {
-        f.hi = *reinterpret_cast<const bf16x8*>(row + 16 * (g ^ sw));
-        f.lo = *reinterpret_cast<const bf16x8*>(row + 16 * ((4 + g) ^ sw));
-    }
-    static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc, 0, 0, 0);
-    }
-};
 
 // Row indices (in packed rows) of the operands of one segment.
 struct SegRows {
@@ -267,26 +178,6 @@ __global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ 
     store_tile<P, WM, WN>(S, pass, beta, m0, n0, vm, vn, lane, acc);
 }
 
-// MFMAs over one LDS stage for a wave's MB x NB blocks.  FULL skips the
-// per-block edge tests (interior tiles), keeping the MFMA stream branch-free.
-template <class P, int MB, int NB, int RS, bool FULL>
-__device__ __forceinline__ void lds_stage(typename P::Acc (&acc)[MB][NB], const char* As, const char* Bs, int g,
-                                          int sw, int vm, int vn) {
-#pragma unroll
-    for (int sub = 0; sub < P::NSUB; ++sub) {
-        typename P::Frag fa[MB], fb[NB];
-#pragma unroll
-        for (int a = 0; a < MB; ++a) P::load_lds(fa[a], As + a * 16 * RS, g, sub, sw);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) P::load_lds(fb[b], Bs + b * 16 * RS, g, sub, sw);
-#pragma unroll
-        for (int a = 0; a < MB; ++a)
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-                if (FULL || (a < vm && b < vn)) P::mma(acc[a][b], fa[a], fb[b]);
-    }
-}
-
 // LDS-staged variant.  Each workgroup (2x2 waves, wave tile WTM x WTN)
 // streams its BM + BN operand rows through two LDS stages of ROWB bytes per
 // row, one barrier per stage; the next stage is fetched into registers while
@@ -299,7 +190,6 @@ __device__ __forceinline__ void lds_stage(typename P::Acc (&acc)[MB][NB], const 
 // counter over all XOR swizzles of this family, the fragment reads (16 rows
 // x 4 lane groups) and the staging writes (8 rows x 8 chunks per wave) are
 // free of bank conflicts.
-__device__ __forceinline__ int lds_swz(int row) { return (((row >> 1) & 1) << 2) | (((row >> 2) & 1) << 1); }
 
 template <class P, int WTM, int WTN, int ROWB, int MINB, bool DIRECT>
 __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __restrict__ slots, int nslot,

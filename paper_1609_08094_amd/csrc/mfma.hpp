@@ -1,0 +1,133 @@
+// MFMA precision traits and LDS staging helpers shared by the matrix
+// kernels (the (T) contraction and the RI-MP2 pair products).
+//
+// A packed operand row holds the summation index fastest (pack.hip); a
+// 16x16 output block is accumulated over chunks of KCH elements:
+//   FP64    v_mfma_f64_16x16x4_f64     4 steps per 16-element chunk
+//   FP32    v_mfma_f32_16x16x4_f32     4 steps per 16-element chunk
+//   BF16X3  v_mfma_f32_16x16x32_bf16   hi*hi + hi*lo + lo*hi per 32-element chunk
+// Within a chunk each lane owns a contiguous run of k; A and B use the same
+// assignment, so the dot product covers every k exactly once.  Output: lane
+// l holds four rows of column l%16 -- rows l/16 + 4r for the FP64
+// instruction, 4(l/16) + r for the FP32-accumulating ones.
+#pragma once
+
+#include "common.hpp"
+
+namespace ccsdt {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // HIP uint4 blocks scalar replacement
+
+// Workgroups are dispatched round-robin over the XCDs; give each XCD a
+// contiguous range of logical work so tiles sharing operand rows share an L2.
+__device__ __forceinline__ int xcd_remap(int bid, int total) {
+    const int q = total / NXCD, r = total % NXCD;
+    const int x = bid % NXCD, idx = bid / NXCD;
+    return x * q + min(x, r) + idx;
+}
+
+struct PrecF64 {
+    using E = double;
+    using W = double;
+    using Acc = f64x4;
+    static constexpr int KCH = 16;
+    static constexpr int UNITS = 1;
+    struct Frag { f64x4 x; };
+    static __device__ __forceinline__ int out_row(int lane, int r) { return (lane >> 4) + 4 * r; }
+    static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
+        f.x = *reinterpret_cast<const GLOBAL f64x4*>(gp(row + c * 16 + 4 * (lane >> 4)));
+    }
+    // LDS staging (128-byte rows of eight 16-byte chunks, see contract_lds_kernel).
+    static constexpr int NSUB = 1;     // k sub-steps per 128-byte LDS row chunk set
+    static constexpr bool SPLIT = true;  // a lane's 32 bytes live in LDS chunks g and 4 + g
+    static __device__ __forceinline__ void load_lds(Frag& f, const char* row, int g, int sub, int sw) {
+        const double2 x0 = *reinterpret_cast<const double2*>(row + 16 * (g ^ sw));
+        const double2 x1 = *reinterpret_cast<const double2*>(row + 16 * ((4 + g) ^ sw));
+        f.x = f64x4{x0.x, x0.y, x1.x, x1.y};
+    }
+    static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[0], b.x[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[1], b.x[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[2], b.x[2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[3], b.x[3], acc, 0, 0, 0);
+    }
+};
+
+struct PrecF32 {
+    using E = float;
+    using W = float;
+    using Acc = f32x4;
+    static constexpr int KCH = 16;
+    static constexpr int UNITS = 1;
+    struct Frag { f32x4 x; };
+    static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+    static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
+        f.x = *reinterpret_cast<const GLOBAL f32x4*>(gp(row + c * 16 + 4 * (lane >> 4)));
+    }
+    static constexpr int NSUB = 2;
+    static constexpr bool SPLIT = false;  // sub-step s, lane group g reads LDS chunk 4 s + g
+    static __device__ __forceinline__ void load_lds(Frag& f, const char* row, int g, int sub, int sw) {
+        f.x = *reinterpret_cast<const f32x4*>(row + 16 * ((4 * sub + g) ^ sw));
+    }
+    static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[0], b.x[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[1], b.x[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[2], b.x[2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[3], b.x[3], acc, 0, 0, 0);
+    }
+};
+
+struct PrecB3 {
+    using E = uint16_t;
+    using W = float;
+    using Acc = f32x4;
+    static constexpr int KCH = 32;
+    static constexpr int UNITS = 2;
+    struct Frag { bf16x8 hi, lo; };
+    static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+    static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
+        const GLOBAL E* p = gp(row + (c * 4 + (lane >> 4)) * 16);
+        f.hi = *reinterpret_cast<const GLOBAL bf16x8*>(p);
+        f.lo = *reinterpret_cast<const GLOBAL bf16x8*>(p + 8);
+    }
+    static constexpr int NSUB = 1;
+    static constexpr bool SPLIT = true;  // hi of group g in LDS chunk g, lo in chunk 4 + g
+    static __device__ __forceinline__ void load_lds(Frag& f, const char* row, int g, int sub, int sw) {
+        f.hi = *reinterpret_cast<const bf16x8*>(row + 16 * (g ^ sw));
+        f.lo = *reinterpret_cast<const bf16x8*>(row + 16 * ((4 + g) ^ sw));
+    }
+    static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc, 0, 0, 0);
+    }
+};
+
+// Workgroup-row swizzle of the 16-byte LDS chunks of a 128-byte stage row
+// (see the LDS-staged contraction kernel for the layout it serves).
+__device__ __forceinline__ int lds_swz(int row) { return (((row >> 1) & 1) << 2) | (((row >> 2) & 1) << 1); }
+
+// MFMAs over one LDS stage for a wave's MB x NB blocks.  FULL skips the
+// per-block edge tests (interior tiles), keeping the MFMA stream branch-free.
+template <class P, int MB, int NB, int RS, bool FULL>
+__device__ __forceinline__ void lds_stage(typename P::Acc (&acc)[MB][NB], const char* As, const char* Bs, int g,
+                                          int sw, int vm, int vn) {
+#pragma unroll
+    for (int sub = 0; sub < P::NSUB; ++sub) {
+        typename P::Frag fa[MB], fb[NB];
+#pragma unroll
+        for (int a = 0; a < MB; ++a) P::load_lds(fa[a], As + a * 16 * RS, g, sub, sw);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) P::load_lds(fb[b], Bs + b * 16 * RS, g, sub, sw);
+#pragma unroll
+        for (int a = 0; a < MB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if (FULL || (a < vm && b < vn)) P::mma(acc[a][b], fa[a], fb[b]);
+    }
+}
+
+}  // namespace ccsdt

@@ -37,6 +37,12 @@ CONFIGS = {
     "C2": dict(o=30, v=400),
     "C3": dict(o=40, v=600),
 }
+# RI-MP2 workloads: the smallest alanine-chain size of the paper's RI-MP2
+# timings (o, v, naux), and a small one for parity tests.
+MP2_CONFIGS = {
+    "M0": dict(o=8, v=60, naux=150),
+    "M1": dict(o=119, v=2546, naux=5852),
+}
 BATCH_NPROB = 64
 BATCH_O_RANGE = (4, 16)
 BATCH_V_RANGE = (40, 160)
@@ -205,3 +211,36 @@ def make_problem_device(o: int, v: int, seed: int = 0, naux: int | None = None,
     return out
 
 
+
+
+def make_mp2_problem(o: int, v: int, naux: int, seed: int = 0, device=None) -> dict:
+    """RI-MP2 inputs: eps_o ~ U[-2.0, -0.3], eps_v ~ U[0.2, 5.0] and fitting
+    coefficients c_ov[i][a][Q] ~ N(0, 0.1^2), drawn in that order from
+    ``default_rng(seed)``, c_ov one occupied index at a time.  With ``device``
+    the coefficients go to torch tensors on it, row by row, so that the host
+    never holds all of them."""
+    rng = np.random.default_rng(seed)
+    eps_o = rng.uniform(-2.0, -0.3, size=o)
+    eps_v = rng.uniform(0.2, 5.0, size=v)
+    out = dict(nocc=o, nvirt=v, naux=naux)
+    if device is None:
+        c = np.empty((o, v, naux))
+        for i in range(o):
+            c[i] = rng.normal(0.0, 0.1, size=(v, naux))
+        out.update(eps_o=eps_o, eps_v=eps_v, c_ov=c)
+        return out
+    import torch
+    c = torch.empty((o, v, naux), dtype=torch.float64, device=device)
+    for i in range(o):
+        c[i].copy_(torch.from_numpy(rng.normal(0.0, 0.1, size=(v, naux))))
+    out.update(eps_o=torch.from_numpy(eps_o).to(device), eps_v=torch.from_numpy(eps_v).to(device), c_ov=c)
+    return out
+
+
+def mp2_from_factors(o: int, v: int, seed: int = 0, naux: int | None = None) -> dict:
+    """Tiny RI-MP2 problem whose coefficients are the ov block of the (T)
+    recipe's symmetric factor B, c_ov[i][a][Q] = B^Q_{i,o+a}, together with
+    the full ERI tensor built from all of B (for the spin-orbital check)."""
+    B, eps_o, eps_v, _ = draw_factors(o, v, seed, naux)
+    return dict(nocc=o, nvirt=v, naux=B.shape[0], eps_o=eps_o, eps_v=eps_v,
+                c_ov=np.ascontiguousarray(B[:, :o, o:].transpose(1, 2, 0)), eri=full_eri(B))

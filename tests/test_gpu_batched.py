@@ -171,5 +171,5 @@ def test_autotune_and_plans(ccsdt_mod):
     ctx.plan_set("fp64", 130, -1)
     assert ctx.plan_get("fp64", 130) == 6
     with pytest.raises(ccsdt_mod.CcsdtError):
-        ctx.plan_set("fp64", 130, 8)
+        ctx.plan_set("fp64", 130, ccsdt_mod.NTILE_CFG)
     ctx.close()
