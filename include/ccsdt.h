@@ -181,8 +181,11 @@ int ccsdt_triple_energies_df(ccsdt_context* ctx, const ccsdt_problem_df* prob, i
  * Input c_ov[i][a][Q] = C^Q_ai (o*v*naux float64, device, Q fastest): the
  * fitting coefficients of eq. fitting_coef, computed by the caller.
  * For each pair i <= j the library forms G_ij[a][b] = g_aibj as one matrix
- * product over Q (precision as for (T): FP64, FP32 or BF16X3 products; the
- * denominators and every sum in FP64) and E = sum_i e_ii + 2 sum_{i<j} e_ij.
+ * product over Q (FP64 or FP32 MFMA; for CCSDT_BF16X3 the BF16 split with
+ * all four products hi*hi + hi*lo + lo*hi + lo*lo, because the diagonal
+ * g_aiai are sums of squares, on which dropping lo*lo is a one-signed bias;
+ * the denominators and every sum in FP64) and
+ * E = sum_i e_ii + 2 sum_{i<j} e_ij.
  * Limits: nocc <= 1024, nvirt <= 8192, naux <= 65536; CCSDT_EDENOM unless
  * max(eps_o) < min(eps_v). */
 typedef struct ccsdt_mp2_problem {

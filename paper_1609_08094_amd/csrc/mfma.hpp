@@ -106,6 +106,20 @@ struct PrecB3 {
     }
 };
 
+// BF16 split products with the lo*lo term kept (four MFMAs per chunk).  For
+// sums of squares (the diagonal RI-MP2 integrals g_aiai) the dropped lo*lo
+// term of PrecB3 is a one-signed bias of about 2^-16 relative; with it the
+// remaining error is the signed residual of the two-term split and the FP32
+// accumulation.
+struct PrecB4 : PrecB3 {
+    static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.lo, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc, 0, 0, 0);
+    }
+};
+
 // Workgroup-row swizzle of the 16-byte LDS chunks of a 128-byte stage row
 // (see the LDS-staged contraction kernel for the layout it serves).
 __device__ __forceinline__ int lds_swz(int row) { return (((row >> 1) & 1) << 2) | (((row >> 2) & 1) << 1); }

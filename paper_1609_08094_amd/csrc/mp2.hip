@@ -6,11 +6,11 @@
 // For an ordered pair (i, j) let G_ij[a][b] = g_aibj = <C_i[a], C_j[b]> (rows
 // of the fitting coefficients, Q fastest); then g_ajbi = G_ij[b][a], and the
 // pair energy e_ij = - sum_ab G(2G - G^T)/D is symmetric in (i, j).  The
-// library forms G_ij for i <= j (one batched NT product per chunk of pairs,
-// precision as in the (T) contraction: FP64, FP32 or BF16x3 on MFMA) into a
-// pair buffer, then an FP64 energy kernel reads each 64 x 64 block of G_ij
-// together with its transposed partner, and E = sum_i e_ii + 2 sum_{i<j} e_ij
-// is summed in a fixed order.
+// library forms G_ij for i <= j (one batched NT product per chunk of pairs on
+// MFMA: FP64, FP32, or the BF16 split with all four hi/lo products, since the
+// diagonal g_aiai are sums of squares) into a pair buffer; then an FP64
+// energy kernel reads each 64 x 64 block of G_ij together with its transposed
+// partner, and E = sum_i e_ii + 2 sum_{i<j} e_ij is summed in a fixed order.
 #include "common.hpp"
 #include "mfma.hpp"
 #include "pack_out.hpp"
@@ -241,8 +241,8 @@ hipError_t launch_mp2_gemm(int prec, const void* cpk, const int2* d_pairs, int n
             hipLaunchKernelGGL(mp2_gemm_kernel<PrecF32>, dim3(total), dim3(256), 0, s, cpk, d_pairs, v, Kq, tiles,
                                total, static_cast<float*>(gbuf));
             break;
-        case P_BF16X3:
-            hipLaunchKernelGGL(mp2_gemm_kernel<PrecB3>, dim3(total), dim3(256), 0, s, cpk, d_pairs, v, Kq, tiles,
+        case P_BF16X3:  // lo*lo kept: see PrecB4
+            hipLaunchKernelGGL(mp2_gemm_kernel<PrecB4>, dim3(total), dim3(256), 0, s, cpk, d_pairs, v, Kq, tiles,
                                total, static_cast<float*>(gbuf));
             break;
         default: return hipErrorInvalidValue;
