@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
         CCSDT_GLOAD(0);
         CCSDT_LSTORE(0);
     }
-    __syncthreads();
+    lds_dma_barrier();
     const bool active = vm > 0 && vn > 0;
     int sg_next = 0, c_next = 0;
     for (int step = 0; step < nsteps; ++step) {
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
                 lds_stage<P, MB, NB, RS, false>(acc, As, Bs, g, sw, vm, vn);
         }
         if constexpr (!DIRECT) CCSDT_LSTORE(buf ^ 1);
-        __syncthreads();
+        lds_dma_barrier();
     }
 #undef CCSDT_SET_PTRS
 #undef CCSDT_GLOAD
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(NBAT * (128 / WTM) * (128 / WTN) * 64, MINB) void c
 
     set_rows(0);
     gload(0, 0);
-    __syncthreads();
+    lds_dma_barrier();
     const bool active = vm > 0 && vn > 0;
     bool dep_cur = depA;
     int sg_next = 0, c_next = 0;
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(NBAT * (128 / WTM) * (128 / WTN) * 64, MINB) void c
             else
                 lds_stage<P, MB, NB, RS, false>(acc, As, Bs, g, sw, vm, vn);
         }
-        __syncthreads();
+        lds_dma_barrier();
     }
     if (active) store_tile<P, MB, NB>(S, pass, beta, m0, n0, vm, vn, lane, acc);
 }
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(NBAT * (128 / WTM) * (128 / WTN) * 64, MINB) void c
     set_rows(0);
     request(0);
     request(1);
-    __syncthreads();
+    lds_dma_barrier();
     StageFrags<P, MB, NB> f0, f1;
     read_frags<P, MB, NB, RS>(f0, a_ptr(0, 0), b_ptr(0, 0), g, sw);
     const bool active = vm > 0 && vn > 0;
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(NBAT * (128 / WTM) * (128 / WTN) * 64, MINB) void c
         for (int h = 0; h < 2; ++h) {
             const int st = step + h;
             if (h == 1 && st >= nsteps) break;
-            __syncthreads();
+            lds_dma_barrier();
             request(h);  // stage st + 2 into buffer st % 2 (= h)
             __builtin_amdgcn_sched_barrier(0);
             const int nst = min(st + 1, nsteps - 1);
@@ -642,6 +642,7 @@ static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int tot
         case 9: hipLaunchKernelGGL((contract_bat_kernel<P, 64, 64, 2, 1>), dim3(total), dim3(512), 0, s, d_slots, nslot, total); break;
         case 10: hipLaunchKernelGGL((contract_pipe_kernel<P, 128, 64, 2, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 11: hipLaunchKernelGGL((contract_pipe_kernel<P, 64, 64, 2, 1>), dim3(total), dim3(512), 0, s, d_slots, nslot, total); break;
+        case 12: hipLaunchKernelGGL((contract_pipe_kernel<P, 64, 64, 1, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -120,6 +120,16 @@ struct PrecB4 : PrecB3 {
     }
 };
 
+// Barrier after which the global_load_lds transfers of every wave have
+// landed in LDS.  A global_load_lds is a load whose LDS write completes with
+// the vector-memory counter; the fence of __syncthreads need not wait for
+// outstanding loads (whether the compiler adds that wait depends on the code
+// around the barrier), so the wait is explicit.
+__device__ __forceinline__ void lds_dma_barrier() {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+}
+
 // Workgroup-row swizzle of the 16-byte LDS chunks of a 128-byte stage row
 // (see the LDS-staged contraction kernel for the layout it serves).
 __device__ __forceinline__ int lds_swz(int row) { return (((row >> 1) & 1) << 2) | (((row >> 2) & 1) << 1); }

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256, 2) void mp2_gemm_kernel(const void* __restrict
                                          (__attribute__((address_space(3))) void*)dst, 16, 0, 0); \
     }
     MP2_GLOAD(0, 0);
-    __syncthreads();
+    lds_dma_barrier();
     const bool active = vm > 0 && vn > 0;
     for (int step = 0; step < nsteps; ++step) {
         const int buf = step & 1;
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256, 2) void mp2_gemm_kernel(const void* __restrict
             else
                 lds_stage<P, MB, NB, RS, false>(acc, As, Bs, g, sw, vm, vn);
         }
-        __syncthreads();
+        lds_dma_barrier();
     }
 #undef MP2_GLOAD
     if (!active) return;

@@ -170,7 +170,7 @@ def tile_cases():
     return cases
 
 
-@pytest.mark.parametrize("cfg", list(range(12)))
+@pytest.mark.parametrize("cfg", list(range(13)))
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_every_tile_config(ctx, tile_cases, cfg, prec, monkeypatch):
     monkeypatch.setenv("CCSDT_TILE", str(cfg))
@@ -181,6 +181,48 @@ def test_every_tile_config(ctx, tile_cases, cfg, prec, monkeypatch):
             assert abs(E - ref[0]) <= 1e-10 * abs(ref[1])
         else:
             assert abs(E - ref[0]) <= max(mixed_tol(ref[0]), 2 * U_TERM[prec] * 1e-2 * abs(ref[1]))
+
+
+@pytest.fixture(scope="module")
+def hbm_case():
+    """A problem whose packed operands (4.6 GB in FP64) live in HBM far beyond
+    the caches, so that staging latencies are those of the large workloads."""
+    d = synth.make_problem_device(16, 320, seed=720, device="cuda")
+    torch.cuda.synchronize()
+    trips = [(0, 1, 2), (3, 7, 15), (5, 9, 12), (2, 2, 11), (4, 8, 8)]
+    return d, trips
+
+
+def test_tile_configs_agree_at_hbm_scale(ctx, hbm_case, monkeypatch):
+    """Every tile configuration against the register-direct one (no LDS
+    staging), per triple, at a size where operands stream from HBM; one
+    triple of the reference also against the oracle."""
+    d, trips = hbm_case
+    monkeypatch.setenv("CCSDT_TILE", "0")
+    say("hbm scale reference cfg 0 fp64")
+    ref = ctx.triple_energies(d, trips, "fp64")
+    host = {f: d[f].cpu().numpy() for f in ("eps_o", "eps_v", "t1", "t2", "ovoo", "ovov")}
+    i, j, k = trips[0]
+
+    class Slices:  # serves vvvo[..., q] for the triple's occupied indices only
+        def __init__(self):
+            self.s = {q: np.ascontiguousarray(d["vvvo"][..., q].cpu().numpy()) for q in (i, j, k)}
+
+        def __getitem__(self, key):
+            return self.s[key[-1]]
+
+    vv = Slices()
+    o_ref = T.triple_restricted(i, j, k, host["eps_o"], host["eps_v"], host["t1"], host["t2"], vv,
+                                host["ovoo"], host["ovov"])
+    assert abs(ref[0][0] - o_ref[0]) <= 1e-10 * abs(o_ref[1])
+    for cfg in range(1, 13):
+        monkeypatch.setenv("CCSDT_TILE", str(cfg))
+        for prec in ("fp64", "fp32", "bf16x3"):
+            say(f"hbm scale cfg {cfg} {prec}")
+            got = ctx.triple_energies(d, trips, prec)
+            for g, r in zip(got, ref):
+                tol = 1e-12 if prec == "fp64" else 1e-6
+                assert abs(g[0] - r[0]) <= tol * abs(r[1]), (cfg, prec, g, r)
 
 
 # ------------------------------------------------------------------- invariants
