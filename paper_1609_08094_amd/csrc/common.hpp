@@ -111,13 +111,17 @@ __host__ __device__ inline int64_t w_index(int a, int b, int c, int nb) {
 // 128x64, 9: eight waves of 64x64).  10-11: as 8-9 with the fragments of the
 // next stage read into registers while the current stage's MFMAs run.  12:
 // that prefetching kernel with one batch index and 2x2 waves of 64x64 (the
-// shape of 6).
+// shape of 6).  13-15: batch-shared deep-ring kernels with NSTAGE - 1 stages
+// in flight (13: two batch indices, eight waves of 64x64, three stages;
+// 14: one batch index, 2x2 waves of 64x64, four stages; 15: two batch
+// indices, four waves of 128x64, three stages).
 struct TileCfg { int bm, bn, lds, nbat; };
-constexpr int NTILE_CFG = 13;
+constexpr int NTILE_CFG = 16;
 constexpr TileCfg TILE_CFGS[NTILE_CFG] = {
     {64, 64, 0, 1},   {128, 64, 0, 1},  {128, 128, 0, 1}, {128, 128, 1, 1}, {128, 256, 1, 1},
     {64, 128, 1, 1},  {128, 128, 2, 1}, {128, 256, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 2},
-    {128, 128, 2, 2}, {128, 128, 2, 2}, {128, 128, 2, 1}};
+    {128, 128, 2, 2}, {128, 128, 2, 2}, {128, 128, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 1},
+    {128, 128, 2, 2}};
 inline int tile_m(int cfg) { return TILE_CFGS[cfg].bm; }
 inline int tile_n(int cfg) { return TILE_CFGS[cfg].bn; }
 inline int tile_nbat(int cfg) { return TILE_CFGS[cfg].nbat; }

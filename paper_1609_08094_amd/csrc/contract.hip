@@ -163,11 +163,7 @@ __global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ 
 #pragma unroll
                 for (int b = 0; b < WN; ++b) if (b < vn) P::load(nb[b], pb[b], c + 1, lane);
             }
-#pragma unroll
-            for (int a = 0; a < WM; ++a)
-#pragma unroll
-                for (int b = 0; b < WN; ++b)
-                    if (a < vm && b < vn) P::mma(acc[a][b], fa[a], fb[b]);
+            mma_blocks<P, WM, WN, false>(acc, fa, fb, vm, vn);
 #pragma unroll
             for (int a = 0; a < WM; ++a) fa[a] = na[a];
 #pragma unroll
@@ -627,6 +623,150 @@ __global__ __launch_bounds__(NBAT * (128 / WTM) * (128 / WTN) * 64, MINB) void c
     if (active) store_tile<P, MB, NB>(S, pass, beta, m0, n0, vm, vn, lane, acc);
 }
 
+// Deep-ring variant of the batch-shared kernel: NSTAGE LDS stages, of which
+// NSTAGE - 1 are in flight (global_load_lds) while one feeds the MFMAs, so
+// that a stage is requested NSTAGE - 1 steps before it is used and HBM/L2
+// latency hides behind that many steps of matrix work.  Per step: wait until
+// only the NSTAGE - 2 most recent stages are outstanding (the vector-memory
+// counter completes loads in issue order), barrier (the stage has landed for
+// every wave, and every wave has finished with the previous stage's buffer),
+// request the stage NSTAGE - 1 ahead into that buffer, then read fragments
+// and run the MFMAs of the current stage.  Tiles, rows and swizzle as
+// contract_bat_kernel.
+template <int N>
+__device__ __forceinline__ void ring_barrier() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+template <class P, int WTM, int WTN, int NBAT, int NSTAGE, int MINB>
+__global__ __launch_bounds__(NBAT * (128 / WTM) * (128 / WTN) * 64, MINB) void contract_ring_kernel(
+    const Slot* __restrict__ slots, int nslot, int total) {
+    constexpr int BM = 128, BN = 128;
+    constexpr int WPB = (BM / WTM) * (BN / WTN);
+    constexpr int NT = 64 * NBAT * WPB;
+    constexpr int RS = 128;
+    constexpr int ROWS = 128 * (1 + NBAT);
+    constexpr int TPR = RS / 16;
+    constexpr int RPP = NT / TPR;
+    constexpr int NP = ROWS / RPP;
+    static_assert(ROWS % RPP == 0, "rows must split evenly over the threads");
+    static_assert(RPP % 8 == 0, "staging rows must keep the swizzle bits");
+    static_assert(NSTAGE >= 3, "at least two stages in flight");
+    constexpr int MB = WTM / 16, NB = WTN / 16;
+    __shared__ __attribute__((aligned(16))) char lds[NSTAGE * ROWS * RS];
+
+    const int bid = xcd_remap(blockIdx.x, total);
+    int pass, bgrp, tmi, tni;
+    const Slot* S = find_slot(slots, nslot, bid, pass, bgrp, tmi, tni);
+    const int v = S->v, o = S->o, Kp = S->Kp;
+    const int mt0 = tmi * BM, nt0 = tni * BN;
+    const int beta0 = bgrp * NBAT;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wb = wave / WPB, wsub = wave % WPB;
+    const int wm = wsub / (BN / WTN), wn = wsub % (BN / WTN);
+    const int beta = beta0 + wb;
+    const int m0 = mt0 + wm * WTM, n0 = nt0 + wn * WTN;
+    const int vm = beta < v ? max(0, min(MB, (v - m0 + 15) / 16)) : 0;
+    const int vn = max(0, min(NB, (v - n0 + 15) / 16));
+
+    const int64_t rowbytes = (int64_t)Kp * P::UNITS * sizeof(typename P::E);
+    const int csteps = (int)(rowbytes / RS);
+    const int nsteps = NSEG * csteps;
+    const char* G = static_cast<const char*>(S->gc);
+    const char* T = static_cast<const char*>(S->tc);
+    const int lrow = threadIdx.x / TPR;
+    const int pch = (lane & 7) ^ lds_swz(lrow);
+    const int src_col = (P::SPLIT ? (((pch & 3) << 1) | (pch >> 2)) : pch) * 16;
+    const int wave_row0 = wave * (64 / TPR);
+
+    const char* rbase[NP];
+    typename P::Acc acc[MB][NB];
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = typename P::Acc{};
+
+    // In both passes the batch-dependent operand is A in segment 0 and B in
+    // segments 1 and 2.
+    auto set_rows = [&](int sg) {
+        const SegRows g = segment(pass, sg, S->i, S->j, S->k, o, v);
+        const bool depA = sg == 0;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int r = lrow + p * RPP;
+            int64_t row;
+            if (r < 128) {
+                row = depA ? g.b0 + (int64_t)min(nt0 + r, v - 1) * g.bN : g.a0 + (int64_t)min(mt0 + r, v - 1) * g.aM;
+            } else {
+                const int bb = min(beta0 + (r - 128) / 128, v - 1), rr = (r - 128) % 128;
+                row = depA ? g.a0 + bb * g.aB + (int64_t)min(mt0 + rr, v - 1) * g.aM
+                           : g.b0 + bb * g.bB + (int64_t)min(nt0 + rr, v - 1) * g.bN;
+            }
+            const bool fromG = (r < 128) == !depA ? g.aG : g.bG;
+            rbase[p] = (fromG ? G : T) + row * rowbytes + src_col;
+        }
+    };
+    // Request the next stage (past the last one, the last chunk again) into buf.
+    int ld_sg = 0, ld_c = -1;
+    auto request = [&](int buf) {
+        if (!(ld_sg == NSEG - 1 && ld_c == csteps - 1)) {
+            if (++ld_c == csteps) {
+                ld_c = 0;
+                ++ld_sg;
+                set_rows(ld_sg);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            char* dst = lds + buf * (ROWS * RS) + (wave_row0 + p * RPP) * RS;
+            __builtin_amdgcn_global_load_lds((const GLOBAL void*)gp(rbase[p] + (int64_t)ld_c * RS),
+                                             (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+        }
+    };
+
+    set_rows(0);
+#pragma unroll
+    for (int s = 0; s < NSTAGE - 1; ++s) request(s);
+    const bool active = vm > 0 && vn > 0;
+    const bool full = vm == MB && vn == NB;
+    const int g = lane >> 4;
+    const int sw = lds_swz(lane & 15);
+    int buf = 0;                 // buffer of stage `step`
+    int lbuf = NSTAGE - 1;       // buffer of stage step + NSTAGE - 1
+    for (int step = 0; step < nsteps; ++step) {
+        ring_barrier<(NSTAGE - 2) * NP>();
+        request(lbuf);
+        __builtin_amdgcn_sched_barrier(0);
+        if (active) {
+            const bool dep = step < csteps;
+            const char* st = lds + buf * (ROWS * RS);
+            const int arow = dep ? 128 * (1 + wb) + wm * WTM : wm * WTM;
+            const int brow = dep ? wn * WTN : 128 * (1 + wb) + wn * WTN;
+            const char* As = st + (arow + (lane & 15)) * RS;
+            const char* Bs = st + (brow + (lane & 15)) * RS;
+            constexpr bool ONE_WAVE_PER_SIMD = NT == 256;
+            if constexpr (ONE_WAVE_PER_SIMD) {
+                if (full)
+                    lds_stage_pm<P, MB, NB, RS, true>(acc, As, Bs, g, sw, vm, vn);
+                else
+                    lds_stage_pm<P, MB, NB, RS, false>(acc, As, Bs, g, sw, vm, vn);
+            } else {
+                if (full)
+                    lds_stage<P, MB, NB, RS, true>(acc, As, Bs, g, sw, vm, vn);
+                else
+                    lds_stage<P, MB, NB, RS, false>(acc, As, Bs, g, sw, vm, vn);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        buf = buf == NSTAGE - 1 ? 0 : buf + 1;
+        lbuf = lbuf == NSTAGE - 1 ? 0 : lbuf + 1;
+    }
+    // drain the trailing requests before the workgroup's LDS is released
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (active) store_tile<P, MB, NB>(S, pass, beta, m0, n0, vm, vn, lane, acc);
+}
+
 template <class P>
 static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int total, hipStream_t s) {
     switch (cfg) {
@@ -643,6 +783,9 @@ static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int tot
         case 10: hipLaunchKernelGGL((contract_pipe_kernel<P, 128, 64, 2, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 11: hipLaunchKernelGGL((contract_pipe_kernel<P, 64, 64, 2, 1>), dim3(total), dim3(512), 0, s, d_slots, nslot, total); break;
         case 12: hipLaunchKernelGGL((contract_pipe_kernel<P, 64, 64, 1, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 13: hipLaunchKernelGGL((contract_ring_kernel<P, 64, 64, 2, 3, 1>), dim3(total), dim3(512), 0, s, d_slots, nslot, total); break;
+        case 14: hipLaunchKernelGGL((contract_ring_kernel<P, 64, 64, 1, 4, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 15: hipLaunchKernelGGL((contract_ring_kernel<P, 128, 64, 2, 3, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

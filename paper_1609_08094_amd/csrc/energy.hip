@@ -51,6 +51,13 @@ template <> struct Unpack<double> {
     }
 };
 
+// Each wave of the energy kernel stages into its own LDS region, and the LDS
+// operations of one wave complete in issue order, so the staging loop needs
+// no workgroup barrier (which would make the two waves alternate loading and
+// computing in lockstep); the fence only keeps the compiler from moving LDS
+// accesses across the stage boundary.
+__device__ __forceinline__ void wave_lds_fence() { asm volatile("" ::: "memory"); }
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
@@ -184,7 +191,7 @@ __global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict_
             (&LT[0][0][0])[lane] = tv[0];
             if (lane < 32) (&LT[0][0][0])[lane + 64] = tv[1];
         }
-        __syncthreads();
+        wave_lds_fence();
         if (ok) {
             const int be = lane >> 3, ga = lane & 7;   // (beta, gamma) column of this lane
             const int b = SB * y + be, c = SB * z + ga;
@@ -237,7 +244,7 @@ __global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict_
                 }
             }
         }
-        __syncthreads();
+        wave_lds_fence();
     }
     const double s4 = block_sum(e4, sh);
     const double s5 = block_sum(e5, sh);

@@ -48,11 +48,17 @@ struct PrecF64 {
         const double2 x1 = *reinterpret_cast<const double2*>(row + 16 * ((4 + g) ^ sw));
         f.x = f64x4{x0.x, x0.y, x1.x, x1.y};
     }
+    // the NMMA products of one chunk, in accumulation order
+    static constexpr int NMMA = 4;
+    template <int T>
+    static __device__ __forceinline__ void mma_t(Acc& acc, const Frag& a, const Frag& b) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[T], b.x[T], acc, 0, 0, 0);
+    }
     static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[0], b.x[0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[1], b.x[1], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[2], b.x[2], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[3], b.x[3], acc, 0, 0, 0);
+        mma_t<0>(acc, a, b);
+        mma_t<1>(acc, a, b);
+        mma_t<2>(acc, a, b);
+        mma_t<3>(acc, a, b);
     }
 };
 
@@ -72,11 +78,16 @@ struct PrecF32 {
     static __device__ __forceinline__ void load_lds(Frag& f, const char* row, int g, int sub, int sw) {
         f.x = *reinterpret_cast<const f32x4*>(row + 16 * ((4 * sub + g) ^ sw));
     }
+    static constexpr int NMMA = 4;
+    template <int T>
+    static __device__ __forceinline__ void mma_t(Acc& acc, const Frag& a, const Frag& b) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[T], b.x[T], acc, 0, 0, 0);
+    }
     static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[0], b.x[0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[1], b.x[1], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[2], b.x[2], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[3], b.x[3], acc, 0, 0, 0);
+        mma_t<0>(acc, a, b);
+        mma_t<1>(acc, a, b);
+        mma_t<2>(acc, a, b);
+        mma_t<3>(acc, a, b);
     }
 };
 
@@ -99,10 +110,17 @@ struct PrecB3 {
         f.hi = *reinterpret_cast<const bf16x8*>(row + 16 * (g ^ sw));
         f.lo = *reinterpret_cast<const bf16x8*>(row + 16 * ((4 + g) ^ sw));
     }
+    static constexpr int NMMA = 3;
+    template <int T>
+    static __device__ __forceinline__ void mma_t(Acc& acc, const Frag& a, const Frag& b) {
+        if constexpr (T == 0) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
+        if constexpr (T == 1) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc, 0, 0, 0);
+        if constexpr (T == 2) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc, 0, 0, 0);
+    }
     static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc, 0, 0, 0);
+        mma_t<0>(acc, a, b);
+        mma_t<1>(acc, a, b);
+        mma_t<2>(acc, a, b);
     }
 };
 
@@ -112,11 +130,19 @@ struct PrecB3 {
 // remaining error is the signed residual of the two-term split and the FP32
 // accumulation.
 struct PrecB4 : PrecB3 {
+    static constexpr int NMMA = 4;
+    template <int T>
+    static __device__ __forceinline__ void mma_t(Acc& acc, const Frag& a, const Frag& b) {
+        if constexpr (T == 0) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.lo, acc, 0, 0, 0);
+        if constexpr (T == 1) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
+        if constexpr (T == 2) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc, 0, 0, 0);
+        if constexpr (T == 3) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc, 0, 0, 0);
+    }
     static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.lo, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc, 0, 0, 0);
+        mma_t<0>(acc, a, b);
+        mma_t<1>(acc, a, b);
+        mma_t<2>(acc, a, b);
+        mma_t<3>(acc, a, b);
     }
 };
 
@@ -133,6 +159,22 @@ __device__ __forceinline__ void lds_dma_barrier() {
 // Workgroup-row swizzle of the 16-byte LDS chunks of a 128-byte stage row
 // (see the LDS-staged contraction kernel for the layout it serves).
 __device__ __forceinline__ int lds_swz(int row) { return (((row >> 1) & 1) << 2) | (((row >> 2) & 1) << 1); }
+
+// The MFMAs of one chunk for a wave's MB x NB blocks, product by product
+// across all blocks, so that consecutive MFMAs never feed each other (each
+// accumulator still sees its products in the order of P::mma).
+template <class P, int MB, int NB, bool FULL, int T = 0>
+__device__ __forceinline__ void mma_blocks(typename P::Acc (&acc)[MB][NB], const typename P::Frag (&fa)[MB],
+                                           const typename P::Frag (&fb)[NB], int vm, int vn) {
+    if constexpr (T < P::NMMA) {
+#pragma unroll
+        for (int a = 0; a < MB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if (FULL || (a < vm && b < vn)) P::template mma_t<T>(acc[a][b], fa[a], fb[b]);
+        mma_blocks<P, MB, NB, FULL, T + 1>(acc, fa, fb, vm, vn);
+    }
+}
 
 // MFMAs over one LDS stage for a wave's MB x NB blocks.  FULL skips the
 // per-block edge tests (interior tiles), keeping the MFMA stream branch-free.
@@ -151,6 +193,23 @@ __device__ __forceinline__ void lds_stage(typename P::Acc (&acc)[MB][NB], const 
 #pragma unroll
             for (int b = 0; b < NB; ++b)
                 if (FULL || (a < vm && b < vn)) P::mma(acc[a][b], fa[a], fb[b]);
+    }
+}
+
+// As lds_stage with the MFMAs issued product by product across all blocks
+// (no MFMA feeds the next one), for kernels with one wave per SIMD, where
+// nothing else hides the latency of a dependent MFMA.
+template <class P, int MB, int NB, int RS, bool FULL>
+__device__ __forceinline__ void lds_stage_pm(typename P::Acc (&acc)[MB][NB], const char* As, const char* Bs, int g,
+                                             int sw, int vm, int vn) {
+#pragma unroll
+    for (int sub = 0; sub < P::NSUB; ++sub) {
+        typename P::Frag fa[MB], fb[NB];
+#pragma unroll
+        for (int a = 0; a < MB; ++a) P::load_lds(fa[a], As + a * 16 * RS, g, sub, sw);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) P::load_lds(fb[b], Bs + b * 16 * RS, g, sub, sw);
+        mma_blocks<P, MB, NB, FULL>(acc, fa, fb, vm, vn);
     }
 }
 
