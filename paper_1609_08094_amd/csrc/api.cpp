@@ -383,15 +383,22 @@ int plan_pipeline(ccsdt_context* ctx, Plan& P, int prec) {
             Slot& S = P.slots[t];
             std::memset(&S, 0, sizeof(Slot));
             S.i = tr.i; S.j = tr.j; S.k = tr.k; S.mult = tr.mult;
+            // e_ijk is invariant under permutations of (i, j, k); a triple with
+            // two equal indices is taken as (p, p, q), for which pass B is pass A
+            // with a and b exchanged and is not run
+            if (!P.one_per_chunk && tr.mult == 3) {
+                if (tr.j == tr.k) { S.i = tr.j; S.j = tr.k; S.k = tr.i; }
+                else if (tr.i == tr.k) { S.i = tr.i; S.j = tr.k; S.k = tr.j; }
+            }
             S.o = L.p.nocc; S.v = v; S.Kp = L.Kp; S.prob = tr.prob;
             S.tiles_m = (v + tile_m(L.cfg) - 1) / tile_m(L.cfg);
             S.tiles_n = (v + tile_n(L.cfg) - 1) / tile_n(L.cfg);
             S.nbw = (v + WB - 1) / WB;
             const int norb = S.nbw * (S.nbw + 1) * (S.nbw + 2) / 6;
             S.bgroups = (v + tile_nbat(L.cfg) - 1) / tile_nbat(L.cfg);
-            const int per = 2 * S.bgroups * S.tiles_m * S.tiles_n;   // pass A then pass B
+            S.npass = (!P.one_per_chunk && S.i == S.j) ? 1 : 2;   // W of both passes for debug_w
+            const int per = S.npass * S.bgroups * S.tiles_m * S.tiles_n;   // pass A then pass B
             S.a_begin = ch.totA; ch.totA += per;
-            S.b_begin = S.a_begin;
             S.e_begin = ch.totE; ch.totE += norb;
             S.part_begin = poff; poff += norb;
             S.trip_index = tr.out_index;

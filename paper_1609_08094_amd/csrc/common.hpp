@@ -41,7 +41,8 @@ struct Slot {
     int o, v, Kp, prob;       // sizes and problem index
     int tiles_m, tiles_n;     // ceil(v / tile edge) along m and n
     int nbw, bgroups;         // W blocks per dimension, ceil(v / WB); batch groups per pass
-    int a_begin, b_begin;     // first contraction workgroup of this slot; unused
+    int a_begin, npass;       // first contraction workgroup of this slot; passes run (2, or 1
+                              // when i = j: then W_B[a][b][c] = W_A[b][a][c] and only W_A is formed)
     int e_begin, trip_index;  // first energy workgroup; index into e_trip
     int64_t part_begin;       // first partial-sum entry (2 doubles each)
     const void* gc;           // packed [p][x][y][Kp] operand of the problem
@@ -114,14 +115,16 @@ __host__ __device__ inline int64_t w_index(int a, int b, int c, int nb) {
 // shape of 6).  13-15: batch-shared deep-ring kernels with NSTAGE - 1 stages
 // in flight (13: two batch indices, eight waves of 64x64, three stages;
 // 14: one batch index, 2x2 waves of 64x64, four stages; 15: two batch
-// indices, four waves of 128x64, three stages).
+// indices, four waves of 128x64, three stages).  16: configuration 6 as a
+// persistent kernel (two resident workgroups per compute unit walking the
+// work items in XCD-synchronous order).
 struct TileCfg { int bm, bn, lds, nbat; };
-constexpr int NTILE_CFG = 16;
+constexpr int NTILE_CFG = 17;
 constexpr TileCfg TILE_CFGS[NTILE_CFG] = {
     {64, 64, 0, 1},   {128, 64, 0, 1},  {128, 128, 0, 1}, {128, 128, 1, 1}, {128, 256, 1, 1},
     {64, 128, 1, 1},  {128, 128, 2, 1}, {128, 256, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 2},
     {128, 128, 2, 2}, {128, 128, 2, 2}, {128, 128, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 1},
-    {128, 128, 2, 2}};
+    {128, 128, 2, 2}, {128, 128, 2, 1}};
 inline int tile_m(int cfg) { return TILE_CFGS[cfg].bm; }
 inline int tile_n(int cfg) { return TILE_CFGS[cfg].bn; }
 inline int tile_nbat(int cfg) { return TILE_CFGS[cfg].nbat; }

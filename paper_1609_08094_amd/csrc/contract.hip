@@ -187,9 +187,14 @@ __global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ 
 // x 4 lane groups) and the staging writes (8 rows x 8 chunks per wave) are
 // free of bank conflicts.
 
-template <class P, int WTM, int WTN, int ROWB, int MINB, bool DIRECT>
-__global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __restrict__ slots, int nslot,
-                                                                  int total) {
+template <int WTM, int WTN, int ROWB>
+constexpr int lds_tile_bytes() { return 2 * (2 * WTM + 2 * WTN) * ROWB; }
+
+// One (slot, pass, batch index, tile) work item of the LDS-staged kernel,
+// logical index `bid`, using the workgroup's LDS `lds`.  Every wave reaches
+// every barrier; on return all LDS traffic of the item has completed.
+template <class P, int WTM, int WTN, int ROWB, bool DIRECT>
+__device__ __forceinline__ void lds_tile(const Slot* __restrict__ slots, int nslot, int bid, char* lds) {
     using E = typename P::E;
     constexpr int NT = 256;
     constexpr int BM = 2 * WTM, BN = 2 * WTN;
@@ -201,9 +206,7 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
     static_assert(ROWS % RPP == 0, "rows must split evenly over the threads");
     constexpr int MB = WTM / 16, NB = WTN / 16;
     static_assert(ROWB == 128, "stage rows are eight 16-byte chunks");
-    __shared__ __attribute__((aligned(16))) char lds[2 * ROWS * RS];
 
-    const int bid = xcd_remap(blockIdx.x, total);
     int pass, beta, tmi, tni;
     const Slot* S = find_slot(slots, nslot, bid, pass, beta, tmi, tni);
     const int v = S->v, o = S->o, Kp = S->Kp;
@@ -325,6 +328,30 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
 #undef CCSDT_GLOAD_DIRECT
 #undef CCSDT_LSTORE
     if (active) store_tile<P, MB, NB>(S, pass, beta, m0, n0, vm, vn, lane, acc);
+}
+
+template <class P, int WTM, int WTN, int ROWB, int MINB, bool DIRECT>
+__global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __restrict__ slots, int nslot,
+                                                                  int total) {
+    __shared__ __attribute__((aligned(16))) char lds[lds_tile_bytes<WTM, WTN, ROWB>()];
+    lds_tile<P, WTM, WTN, ROWB, DIRECT>(slots, nslot, xcd_remap(blockIdx.x, total), lds);
+}
+
+// Persistent form: gridDim.x (a multiple of NXCD) resident workgroups walk the
+// work items.  Workgroup b runs on XCD b % NXCD and takes, within that XCD's
+// contiguous range of logical items, every (gridDim.x / NXCD)-th item from
+// position b / NXCD.  All items cost about the same, so the workgroups of an
+// XCD start their t-th items together and read shared operand rows (the G
+// rows of a batch index, the T rows of a segment) while they are still in
+// that XCD's L2; one-item-per-workgroup launches drift apart and re-fetch them.
+template <class P, int WTM, int WTN, int ROWB, int MINB, bool DIRECT>
+__global__ __launch_bounds__(256, MINB) void contract_lds_persist_kernel(const Slot* __restrict__ slots, int nslot,
+                                                                          int total) {
+    __shared__ __attribute__((aligned(16))) char lds[lds_tile_bytes<WTM, WTN, ROWB>()];
+    const int x = blockIdx.x % NXCD, lw = blockIdx.x / NXCD, per_xcd = gridDim.x / NXCD;
+    const int q = total / NXCD, r = total % NXCD;
+    const int begin = x * q + min(x, r), end = begin + q + (x < r ? 1 : 0);
+    for (int id = begin + lw; id < end; id += per_xcd) lds_tile<P, WTM, WTN, ROWB, DIRECT>(slots, nslot, id, lds);
 }
 
 // Batch-shared variant.  In every segment exactly one operand depends on the
@@ -767,6 +794,21 @@ __global__ __launch_bounds__(NBAT * (128 / WTM) * (128 / WTN) * 64, MINB) void c
     if (active) store_tile<P, MB, NB>(S, pass, beta, m0, n0, vm, vn, lane, acc);
 }
 
+// Resident workgroups for the persistent kernels: `per_cu` per compute unit,
+// rounded to a multiple of NXCD.
+static int persist_grid(int per_cu) {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            cus = n;
+        else
+            cus = 256;
+    }
+    return (cus * per_cu + NXCD - 1) / NXCD * NXCD;
+}
+
 template <class P>
 static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int total, hipStream_t s) {
     switch (cfg) {
@@ -786,6 +828,7 @@ static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int tot
         case 13: hipLaunchKernelGGL((contract_ring_kernel<P, 64, 64, 2, 3, 1>), dim3(total), dim3(512), 0, s, d_slots, nslot, total); break;
         case 14: hipLaunchKernelGGL((contract_ring_kernel<P, 64, 64, 1, 4, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 15: hipLaunchKernelGGL((contract_ring_kernel<P, 128, 64, 2, 3, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 16: hipLaunchKernelGGL((contract_lds_persist_kernel<P, 64, 64, 128, 2, true>), dim3(persist_grid(2)), dim3(256), 0, s, d_slots, nslot, total); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

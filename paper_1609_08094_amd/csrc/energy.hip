@@ -116,6 +116,7 @@ __global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict_
     const int v = S->v, o = S->o, i = S->i, j = S->j, k = S->k, nb = S->nbw;
     const GLOBAL WT* W = gp(static_cast<const WT*>(S->w));                 // W_A
     const GLOBAL WT* WBp = W + (int64_t)nb * nb * nb * (WB * WB * WB);       // W_B
+    const bool onepass = S->npass == 1;
     const GLOBAL double* eps_o = gp(S->eps_o);
     const double eo = eps_o[i] + eps_o[j] + eps_o[k];
     // (pX|qY) = ovov[p][X][q][Y]; Spq[X * rs + Y] = (pX|qY)
@@ -149,8 +150,10 @@ __global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict_
             for (int p = 0; p < 6; ++p) {
                 const int ga = min(SB * P[p][0] + r, v - 1), gb = min(SB * P[p][1] + cc, v - 1);
                 const int64_t off = w_index(ga, gb, SB * P[p][2], nb);
+                // one-pass slot (i = j): W_B[a][b][c] = W_A[b][a][c]
+                const int64_t offB = onepass ? w_index(gb, ga, SB * P[p][2], nb) : off;
                 const GLOBAL u32x4* srcA = (const GLOBAL u32x4*)(W + off);
-                const GLOBAL u32x4* srcB = (const GLOBAL u32x4*)(WBp + off);
+                const GLOBAL u32x4* srcB = (const GLOBAL u32x4*)((onepass ? W : WBp) + offB);
 #pragma unroll
                 for (int g = 0; g < NVL; ++g) {
                     wa[p][g] = srcA[g];
