@@ -110,6 +110,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample", default="0,1,2",
                     help="triples for the CPU baseline and the sampled parity, as i,j,k[;i,j,k]")
+    ap.add_argument("--partial-triples", type=int, default=0, metavar="N",
+                    help="profiling aid: instead of a step, evaluate the N distinct triples (0, 1, 2..N+1) "
+                         "twice (kernel loading, then the run to profile) and print their kernel times")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device to device five times (reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -151,6 +154,22 @@ def main():
     ctx = ccsdt.Context()
     ctx.profile(True)
     stream = torch.cuda.current_stream()
+    if args.partial_triples:
+        trips = [(0, 1, 2 + n) for n in range(args.partial_triples)]
+        run = ctx.triple_energies_df if df else ctx.triple_energies
+        run(dev, trips, args.precision, stream)
+        ctx.profile_reset()
+        e = run(dev, trips, args.precision, stream)
+        torch.cuda.synchronize()
+        prof = {name: ctx.profile_get(name) for name in ccsdt.KERNEL_CLASSES}
+        fl = len(trips) * triple_flops(o, v, 6)
+        n, ms = prof["contract"]
+        print(json.dumps({"partial_triples": trips, "precision": args.precision, "config": args.config,
+                          "kernels_ms": {k: t for k, (c, t) in prof.items()},
+                          "contract_mfma_tflops": MFMA_FACTOR[args.precision] * fl / (ms * 1e-3) / 1e12,
+                          "e": [x[0] for x in e]}), flush=True)
+        ctx.close()
+        return
     log("bench: prime pass (allocation, kernel load)")
     triples = ctx.triple_energies_df if df else ctx.triple_energies
     triples(dev, [(0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)], args.precision, stream)

@@ -92,8 +92,13 @@ __device__ __forceinline__ void decode_orbit(int q, int& A, int& B, int& C) {
 template <class WT>
 __global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict__ slots, int nslot,
                                                          double* __restrict__ partials) {
-    constexpr int RS = SB + 1;            // padded W row (elements)
-    constexpr int PS = SB * RS + 1;       // padded W plane
+    // W sub-block in LDS: element (u, w, t) at u*PS + w*RS + t.  The six
+    // permuted reads of the evaluation loop hold one index fixed and spread
+    // the other two over the lanes; with rows unpadded (RS = SB) and the plane
+    // pitch below, searched over all six patterns for 64 banks of 4 bytes,
+    // every such read is at most 2-way (float) or 3-way (double) conflicted.
+    constexpr int RS = SB;
+    constexpr int PS = sizeof(WT) == 4 ? 69 : 67;
     constexpr int BLK = SB * PS;          // one W sub-block
     constexpr int SRS = SB + 1;           // padded S row (doubles)
     constexpr int SBLK = SB * SRS;        // one S sub-block
