@@ -36,6 +36,25 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(key):
+    """HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes recorded in profiles/traffic.json (scaled by a plain copy's
+    counter readings), or None when absent or taken on other kernel sources."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path)).get(key)
+    except (OSError, ValueError):
+        return None
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def triple_flops(o, v, m):
     return m * (2.0 * v ** 4 + 2.0 * o * v ** 3)
 
@@ -196,6 +215,11 @@ def main():
     achieved = mf * flops_a_per_launch / (avg_a * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     kernels = {k: {"launches": n // max(args.steps, 1), "ms_per_step": t / args.steps} for k, (n, t) in prof.items()}
+    # traffic (bytes per launch) was measured for the default plan of C3 BF16x3
+    traffic = None
+    if args.config == "C3" and args.precision == "bf16x3" and not df and ctx.plan_get(args.precision, v) == 6 \
+            and not os.environ.get("CCSDT_TILE"):
+        traffic = measured_traffic("contract_lds_kernel<PrecB3,64,64,128,2,true>|C3")
 
     sample = [tuple(int(x) for x in s.split(",")) for s in args.sample.split(";") if s]
     parity = None
@@ -231,7 +255,7 @@ def main():
         "energy": {"E": E, "E4": E4, "E5": E5},
         "mfma_util": achieved / peak,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
                      "kernel": "contraction", "avg_launch_ms": avg_a, "launches_per_step": na // args.steps},
         "kernels": kernels,
         "parity_sample": parity,
