@@ -117,14 +117,17 @@ __host__ __device__ inline int64_t w_index(int a, int b, int c, int nb) {
 // 14: one batch index, 2x2 waves of 64x64, four stages; 15: two batch
 // indices, four waves of 128x64, three stages).  16: configuration 6 as a
 // persistent kernel (two resident workgroups per compute unit walking the
-// work items in XCD-synchronous order).
+// work items in XCD-synchronous order).  17-18: direct-to-LDS staging with
+// larger workgroup tiles, 256x256 (2x2 waves of 128x128) and 256x128 (2x2
+// waves of 128x64), one workgroup per compute unit, fewer re-reads of shared
+// operand rows per flop.
 struct TileCfg { int bm, bn, lds, nbat; };
-constexpr int NTILE_CFG = 17;
+constexpr int NTILE_CFG = 19;
 constexpr TileCfg TILE_CFGS[NTILE_CFG] = {
     {64, 64, 0, 1},   {128, 64, 0, 1},  {128, 128, 0, 1}, {128, 128, 1, 1}, {128, 256, 1, 1},
     {64, 128, 1, 1},  {128, 128, 2, 1}, {128, 256, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 2},
     {128, 128, 2, 2}, {128, 128, 2, 2}, {128, 128, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 1},
-    {128, 128, 2, 2}, {128, 128, 2, 1}};
+    {128, 128, 2, 2}, {128, 128, 2, 1}, {256, 256, 2, 1}, {256, 128, 2, 1}};
 inline int tile_m(int cfg) { return TILE_CFGS[cfg].bm; }
 inline int tile_n(int cfg) { return TILE_CFGS[cfg].bn; }
 inline int tile_nbat(int cfg) { return TILE_CFGS[cfg].nbat; }

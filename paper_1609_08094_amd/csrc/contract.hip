@@ -829,6 +829,8 @@ static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int tot
         case 14: hipLaunchKernelGGL((contract_ring_kernel<P, 64, 64, 1, 4, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 15: hipLaunchKernelGGL((contract_ring_kernel<P, 128, 64, 2, 3, 1>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 16: hipLaunchKernelGGL((contract_lds_persist_kernel<P, 64, 64, 128, 2, true>), dim3(persist_grid(2)), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 17: hipLaunchKernelGGL((contract_lds_kernel<P, 128, 128, 128, 1, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 18: hipLaunchKernelGGL((contract_lds_kernel<P, 128, 64, 128, 1, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
