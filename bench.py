@@ -122,9 +122,10 @@ def main():
                          "(o ~ U{4..16}, v ~ U{40..160}) per step through one captured graph; "
                          "M0, M1: RI-MP2 energy (M1: o=119, v=2546, naux=5852)")
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
-    ap.add_argument("--input", default="eri", choices=["eri", "df"],
-                    help="eri: the (vv|vo) block is an input; df: density-fitting factors are the input and "
-                         "the library assembles the (vv|vo) operand on the GPU")
+    ap.add_argument("--input", default="eri", choices=["eri", "df", "host"],
+                    help="eri: the (vv|vo) block is an input in HBM; df: density-fitting factors are the input "
+                         "and the library assembles the (vv|vo) operand on the GPU; host: the (vv|vo) block is "
+                         "in pinned host memory and streamed by the library (PCIe-inclusive)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample", default="0,1,2",
@@ -166,6 +167,12 @@ def main():
     df = args.input == "df"
     dev = synth.make_problem_device(o, v, seed=args.seed, device="cuda", with_vvvo=not df, with_df=df)
     energy = ctx_energy_df if df else ctx_energy
+    if args.input == "host":
+        log("bench: moving vvvo to pinned host memory")
+        h = torch.empty(dev["vvvo"].shape, dtype=torch.float64, pin_memory=True)
+        h.copy_(dev["vvvo"])
+        dev["vvvo"] = h
+        torch.cuda.empty_cache()
     torch.cuda.synchronize()
     log(f"bench: inputs ready in {time.perf_counter() - t0:.1f}s")
 
@@ -249,7 +256,8 @@ def main():
         "dtype": args.precision, "data": "synthetic (density-fitted integrals, MP2 doubles; seeded)",
         "config": {"workload": f"closed-shell (T) {args.config}: o={o} v={v} naux={3 * (o + v)} "
                                f"seed={args.seed}, {args.precision}"
-                               + (", density-fitted (vv|vo) assembled on the GPU" if df else ""),
+                               + (", density-fitted (vv|vo) assembled on the GPU" if df else "")
+                               + (", (vv|vo) streamed from pinned host memory" if args.input == "host" else ""),
                    "input": args.input,
                    "nocc": o, "nvirt": v, "precision": args.precision, "algorithmic_flops": F},
         "energy": {"E": E, "E4": E4, "E5": E5},

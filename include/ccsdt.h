@@ -40,7 +40,14 @@
  * symmetry of the inputs is assumed.
  *
  * Memory and ownership: every input pointer is a DEVICE pointer (for example
- * the data pointer of a contiguous torch.float64 tensor on the HIP device).
+ * the data pointer of a contiguous torch.float64 tensor on the HIP device),
+ * except that vvvo, the largest block (o*v^3), may instead be page-locked
+ * HOST memory (hipHostMalloc, or a torch tensor created with pin_memory):
+ * the library then streams it in chunks of whole rows vvvo[y] through two
+ * device staging buffers (CCSDT_STAGE_BYTES for both, default 2 GiB), the
+ * copy of one chunk overlapping the packing of the previous one (Sec. 3:
+ * tiles of the integrals staged from pinned host memory), and keeps only
+ * the packed operand on the device.  Pageable host memory is rejected.
  * The caller owns the inputs; the library only reads them, during the call,
  * and never frees or retains them.  Outputs named *_host are host pointers.
  * Work runs on the HIP stream passed in (NULL = the default stream); every

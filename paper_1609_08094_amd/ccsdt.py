@@ -110,21 +110,23 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _dev_ptrs(prob: dict, fields) -> list:
+def _dev_ptrs(prob: dict, fields, host_ok=()) -> list:
     import torch
     vals = []
     for f in fields:
         t = prob[f]
-        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous() \
-                or not t.is_cuda:
-            raise ValueError(f"{f} must be a contiguous float64 tensor on the HIP device")
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError(f"{f} must be a contiguous float64 tensor")
+        if not t.is_cuda and not (f in host_ok and t.is_pinned()):
+            raise ValueError(f"{f} must be on the HIP device" + (" or in pinned host memory" if f in host_ok else ""))
         vals.append(ctypes.c_void_p(t.data_ptr()))
     return vals
 
 
 def make_problem_struct(prob: dict) -> Problem:
-    """Problem struct from a dict of contiguous float64 device tensors."""
-    return Problem(int(prob["nocc"]), int(prob["nvirt"]), *_dev_ptrs(prob, FIELDS))
+    """Problem struct from a dict of contiguous float64 tensors on the device
+    (vvvo may also be a pinned host tensor, which the library streams)."""
+    return Problem(int(prob["nocc"]), int(prob["nvirt"]), *_dev_ptrs(prob, FIELDS, host_ok=("vvvo",)))
 
 
 def make_problem_df_struct(prob: dict) -> ProblemDF:

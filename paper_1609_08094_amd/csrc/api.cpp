@@ -91,10 +91,17 @@ struct ccsdt_context {
     GraphEntry graph;
     hipStream_t cap_stream = nullptr;          // private stream used only for graph capture
     int64_t n_captures = 0, n_replays = 0;
+    // streaming of a host-resident vvvo: two device staging buffers, a copy
+    // stream and the events that order copies and packs
+    DevBuf stage;
+    size_t stage_budget = 0;                   // CCSDT_STAGE_BYTES: both staging buffers together
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_copy[2] = {nullptr, nullptr}, ev_pack[2] = {nullptr, nullptr}, ev_start = nullptr;
+    int64_t streamed_bytes = 0;
 
     size_t allocated() const {
         return gc.bytes + tc.bytes + w.bytes + part.bytes + etrip.bytes + slots.bytes + out.bytes + tripbeg.bytes +
-               pdesc.bytes;
+               pdesc.bytes + stage.bytes;
     }
 };
 
@@ -215,6 +222,19 @@ bool is_device_ptr(const void* p) {
     return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
+// Page-locked host memory (hipHostMalloc) that the device can copy from
+// asynchronously.
+bool is_pinned_host_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeHost;
+}
+
 int check_problem(const ccsdt_problem* p, int idx, bool need_vvvo = true) {
     const std::string where = idx >= 0 ? " (problem " + std::to_string(idx) + ")" : "";
     if (!p) return fail(CCSDT_EINVAL, "null problem" + where);
@@ -226,8 +246,10 @@ int check_problem(const ccsdt_problem* p, int idx, bool need_vvvo = true) {
     for (int n = 0; n < 7; ++n) {
         if (n == 4 && !need_vvvo) continue;
         if (!ptrs[n]) return fail(CCSDT_EINVAL, std::string("null pointer ") + names[n] + where);
+        if (n == 4 && is_pinned_host_ptr(ptrs[n])) continue;   // streamed from host memory
         if (!is_device_ptr(ptrs[n]))
-            return fail(CCSDT_EINVAL, std::string(names[n]) + " is not a device pointer" + where);
+            return fail(CCSDT_EINVAL, std::string(names[n]) + " is not a device pointer" +
+                                          (n == 4 ? " or pinned host memory" : "") + where);
     }
     return CCSDT_OK;
 }
@@ -285,6 +307,7 @@ struct ProbLayout {
     const double* bvv;        // density-fitting factors (DF problems only)
     const double* bvo;
     int naux;
+    bool vvvo_host;           // vvvo in pinned host memory: streamed through the staging ring
     int Kp;
     int cfg;
     size_t gc_off, tc_off;  // byte offsets in the pooled pack buffers
@@ -317,9 +340,14 @@ int multiplicity(int i, int j, int k) {
     return 6;
 }
 
+int prepare_streaming(ccsdt_context* ctx, const Plan& P);
+bool is_pinned_host_ptr(const void* p);
+
 // Host phase: tile choice, pooled pack offsets, chunking by the W budget,
 // workspace allocation and the slot table.  Launches nothing.
 int plan_pipeline(ccsdt_context* ctx, Plan& P, int prec) {
+    for (auto& L : P.probs) L.vvvo_host = L.p.vvvo && is_pinned_host_ptr(L.p.vvvo);
+    CHK(prepare_streaming(ctx, P));
     size_t gc_total = 0, tc_total = 0;
     const size_t es = elem_bytes(prec);
     for (auto& L : P.probs) {
@@ -412,6 +440,62 @@ int plan_pipeline(ccsdt_context* ctx, Plan& P, int prec) {
     return CCSDT_OK;
 }
 
+// Particle part of G from a host-resident (pinned) vvvo: chunks of whole
+// rows y (v*v*o doubles each) are copied on the context's copy stream into
+// two staging buffers in turn, and each is packed on stream s as soon as it
+// has landed; a buffer is refilled only after the pack that read it.  The
+// staging buffers are sized by CCSDT_STAGE_BYTES (both together, default
+// 2 GiB, at least one row each).
+// Rows per staging buffer for a problem streamed from host memory.
+int stage_rows(const ccsdt_context* ctx, int o, int v) {
+    const size_t row = (size_t)v * v * o * sizeof(double);
+    return (int)std::max<size_t>(1, std::min<size_t>((size_t)v, ctx->stage_budget / 2 / row));
+}
+
+// Staging buffers, copy stream and events for host-resident vvvo (host phase).
+int prepare_streaming(ccsdt_context* ctx, const Plan& P) {
+    size_t need = 0;
+    for (const auto& L : P.probs)
+        if (L.vvvo_host)
+            need = std::max(need, 2 * (size_t)stage_rows(ctx, L.p.nocc, L.p.nvirt) * L.p.nvirt * L.p.nvirt *
+                                      L.p.nocc * sizeof(double));
+    if (!need) return CCSDT_OK;
+    CHK(ensure(ctx, ctx->stage, need, "staging buffers"));
+    if (!ctx->copy_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
+    for (int b = 0; b < 2; ++b) {
+        if (!ctx->ev_copy[b]) HIPCHK(hipEventCreateWithFlags(&ctx->ev_copy[b], hipEventDisableTiming));
+        if (!ctx->ev_pack[b]) HIPCHK(hipEventCreateWithFlags(&ctx->ev_pack[b], hipEventDisableTiming));
+    }
+    if (!ctx->ev_start) HIPCHK(hipEventCreateWithFlags(&ctx->ev_start, hipEventDisableTiming));
+    return CCSDT_OK;
+}
+
+int stream_pack(ccsdt_context* ctx, const ProbLayout& L, int prec, char* g, hipStream_t s) {
+    const int o = L.p.nocc, v = L.p.nvirt;
+    const size_t row = (size_t)v * v * o * sizeof(double);
+    const int ny = stage_rows(ctx, o, v);
+    // the copies start after the work already queued on s
+    HIPCHK(hipEventRecord(ctx->ev_start, s));
+    HIPCHK(hipStreamWaitEvent(ctx->copy_stream, ctx->ev_start, 0));
+    const char* host = reinterpret_cast<const char*>(L.p.vvvo);
+    char* stage = static_cast<char*>(ctx->stage.p);
+    int c = 0;
+    for (int y0 = 0; y0 < v; y0 += ny, ++c) {
+        const int n = std::min(ny, v - y0);
+        const int b = c & 1;
+        char* buf = stage + (size_t)b * ny * row;
+        if (c >= 2) HIPCHK(hipStreamWaitEvent(ctx->copy_stream, ctx->ev_pack[b], 0));
+        HIPCHK(hipMemcpyAsync(buf, host + (size_t)y0 * row, (size_t)n * row, hipMemcpyHostToDevice,
+                              ctx->copy_stream));
+        HIPCHK(hipEventRecord(ctx->ev_copy[b], ctx->copy_stream));
+        HIPCHK(hipStreamWaitEvent(s, ctx->ev_copy[b], 0));
+        LAUNCH(K_PACK, launch_pack_particle_chunk(prec, o, v, L.Kp, reinterpret_cast<const double*>(buf), y0, n, g, s));
+        HIPCHK(hipEventRecord(ctx->ev_pack[b], s));
+        ctx->streamed_bytes += (int64_t)((size_t)n * row);
+    }
+    return CCSDT_OK;
+}
+
 // Device phase: upload of the slot table (from pinned ``host_slots``), the
 // packs and every chunk's launches, all on stream s.  Nothing here allocates
 // or synchronizes, so the phase can be captured into a graph.  With debug_w
@@ -423,9 +507,14 @@ int enqueue_pipeline(ccsdt_context* ctx, const Plan& P, int prec, hipStream_t s,
     for (const auto& L : P.probs) {
         char* g = static_cast<char*>(ctx->gc.p) + L.gc_off;
         char* t = static_cast<char*>(ctx->tc.p) + L.tc_off;
+        const double* vvvo = L.p.vvvo;
         if (L.bvv)
             LAUNCH(K_ASSEMBLE, launch_assemble_df(prec, L.p.nocc, L.p.nvirt, L.naux, L.Kp, L.bvv, L.bvo, g, s));
-        LAUNCH(K_PACK, launch_pack(prec, L.p.nocc, L.p.nvirt, L.Kp, L.p.vvvo, L.p.t2, L.p.ovoo, g, t, s));
+        if (L.vvvo_host) {
+            CHK(stream_pack(ctx, L, prec, g, s));
+            vvvo = nullptr;
+        }
+        LAUNCH(K_PACK, launch_pack(prec, L.p.nocc, L.p.nvirt, L.Kp, vvvo, L.p.t2, L.p.ovoo, g, t, s));
     }
     const Slot* dslots = static_cast<const Slot*>(ctx->slots.p);
     double* part = static_cast<double*>(ctx->part.p);
@@ -463,6 +552,7 @@ void whole_problem_plan(Plan& P, int nprob, const ccsdt_problem* probs, std::vec
     trip_begin.assign(nprob + 1, 0);
     for (int p = 0; p < nprob; ++p) {
         P.probs[p].p = probs[p];
+        P.probs[p].vvvo_host = is_pinned_host_ptr(probs[p].vvvo);
         const int o = probs[p].nocc;
         trip_begin[p] = (int)P.trips.size();
         for (int i = 0; i < o; ++i)
@@ -653,6 +743,7 @@ int ccsdt_context_create(ccsdt_context** ctx_out) {
     ctx->device = dev;
     ctx->cap = env_size("CCSDT_MAX_DEVICE_BYTES", 0);
     ctx->w_budget = env_size("CCSDT_W_BYTES", (size_t)4 << 30);
+    ctx->stage_budget = env_size("CCSDT_STAGE_BYTES", (size_t)2 << 30);
     *ctx_out = ctx;
     return CCSDT_OK;
 }
@@ -662,6 +753,13 @@ int ccsdt_context_destroy(ccsdt_context* ctx) {
     graph_reset(ctx->graph);
     if (ctx->graph.host) (void)hipHostFree(ctx->graph.host);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->copy_stream) {
+        (void)hipStreamSynchronize(ctx->copy_stream);
+        (void)hipStreamDestroy(ctx->copy_stream);
+    }
+    for (hipEvent_t e : {ctx->ev_copy[0], ctx->ev_copy[1], ctx->ev_pack[0], ctx->ev_pack[1], ctx->ev_start})
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->stage.p) (void)hipFree(ctx->stage.p);
     DevBuf* bufs[] = {&ctx->gc, &ctx->tc, &ctx->w, &ctx->part, &ctx->etrip, &ctx->slots, &ctx->out, &ctx->tripbeg,
                       &ctx->pdesc};
     for (DevBuf* b : bufs)
@@ -726,7 +824,9 @@ static int energy_many(ccsdt_context* ctx, int nprob, const ccsdt_problem* probs
     CHK(check_prec(prec));
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int p = 0; p < nprob; ++p) CHK(check_problem(&probs[p], nprob > 1 ? p : -1));
-    if (nprob > 1 && !ctx->profile && env_int("CCSDT_GRAPH", 1) != 0)
+    bool any_host = false;
+    for (int p = 0; p < nprob; ++p) any_host = any_host || is_pinned_host_ptr(probs[p].vvvo);
+    if (nprob > 1 && !ctx->profile && !any_host && env_int("CCSDT_GRAPH", 1) != 0)
         return energy_graph(ctx, nprob, probs, prec, s, out_host);
 
     prof_start_call(ctx);
@@ -835,6 +935,7 @@ int ccsdt_triple_energies(ccsdt_context* ctx, const ccsdt_problem* prob, int pre
     CHK(check_problem(prob, -1));
     ProbLayout L{};
     L.p = *prob;
+    L.vvvo_host = is_pinned_host_ptr(prob->vvvo);
     return triple_energies_impl(ctx, L, precision, ntrip, ijk_host, hip_stream, out_host);
 }
 

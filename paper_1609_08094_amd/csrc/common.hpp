@@ -59,6 +59,10 @@ struct Slot {
 // With vvvo == nullptr the particle part of G is left to launch_assemble_df.
 hipError_t launch_pack(int prec, int o, int v, int Kp, const double* vvvo, const double* t2,
                        const double* ovoo, void* gc, void* tc, hipStream_t s);
+// Particle part of G from rows y0 .. y0 + ny - 1 of vvvo held in `chunk`
+// (ny * v * v * o doubles, device), for vvvo streamed from host memory.
+hipError_t launch_pack_particle_chunk(int prec, int o, int v, int Kp, const double* chunk, int y0, int ny, void* gc,
+                                      hipStream_t s);
 // Particle part of G from density-fitting factors (see df.hip).
 hipError_t launch_assemble_df(int prec, int o, int v, int naux, int Kp, const double* bvv, const double* bvo,
                               void* gc, hipStream_t s);

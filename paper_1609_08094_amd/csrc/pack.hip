@@ -33,9 +33,11 @@ namespace ccsdt {
 // G[p][x][y].  Grid: (q tiles) x (d tiles) x y, q tiles fastest.
 constexpr int PK_D = 64, PK_Q = 128;
 
+// `vvvo` holds the rows y0 .. y0 + ny - 1 of vvvo[y][d][x][p] (the whole block,
+// or one streamed chunk); the grid covers those rows.
 template <class O>
 __global__ __launch_bounds__(256) void pack_g_particle(const double* __restrict__ vvvo, int o, int v,
-                                                       int Kp, typename O::T* __restrict__ g) {
+                                                       int Kp, typename O::T* __restrict__ g, int y0) {
     __shared__ double tile[PK_D][PK_Q + 1];
     const int64_t nq = (int64_t)v * o;
     const int qtiles = (int)((nq + PK_Q - 1) / PK_Q);
@@ -43,7 +45,8 @@ __global__ __launch_bounds__(256) void pack_g_particle(const double* __restrict_
     const int64_t bid = blockIdx.x;
     const int qt = (int)(bid % qtiles);
     const int dt = (int)((bid / qtiles) % dtiles);
-    const int y = (int)(bid / ((int64_t)qtiles * dtiles));
+    const int yl = (int)(bid / ((int64_t)qtiles * dtiles));   // row within the chunk
+    const int y = y0 + yl;
     const int64_t q0 = (int64_t)qt * PK_Q;
     const int d0 = dt * PK_D;
     const GLOBAL double* src = gp(vvvo);
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(256) void pack_g_particle(const double* __restrict_
         const int d = d0 + dd;
         const int64_t q = q0 + qq;
         double val = 0.0;
-        if (d < v && q < nq) val = src[((int64_t)y * v + d) * nq + q];
+        if (d < v && q < nq) val = src[((int64_t)yl * v + d) * nq + q];
         tile[dd][qq] = val;
     }
     __syncthreads();
@@ -131,7 +134,7 @@ static hipError_t pack_impl(int o, int v, int Kp, const double* vvvo, const doub
     if (vvvo) {
         const int64_t qtiles = ((int64_t)v * o + PK_Q - 1) / PK_Q, dtiles = (v + PK_D - 1) / PK_D;
         hipLaunchKernelGGL(pack_g_particle<O>, dim3((unsigned)(qtiles * dtiles * v)), dim3(256), 0, s, vvvo, o, v,
-                           Kp, g);
+                           Kp, g, 0);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -143,6 +146,24 @@ static hipError_t pack_impl(int o, int v, int Kp, const double* vvvo, const doub
     hipLaunchKernelGGL(pack_t<O>, dim3((unsigned)std::min<int64_t>(trows, (int64_t)1 << 22)), dim3(256), 0, s, t2,
                        ovoo, o, v, Kp, t);
     return hipGetLastError();
+}
+
+template <class O>
+static hipError_t pack_chunk_impl(int o, int v, int Kp, const double* chunk, int y0, int ny, void* gc, hipStream_t s) {
+    const int64_t qtiles = ((int64_t)v * o + PK_Q - 1) / PK_Q, dtiles = (v + PK_D - 1) / PK_D;
+    hipLaunchKernelGGL(pack_g_particle<O>, dim3((unsigned)(qtiles * dtiles * ny)), dim3(256), 0, s, chunk, o, v, Kp,
+                       static_cast<typename O::T*>(gc), y0);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_particle_chunk(int prec, int o, int v, int Kp, const double* chunk, int y0, int ny, void* gc,
+                                      hipStream_t s) {
+    switch (prec) {
+        case P_FP64: return pack_chunk_impl<OutF64>(o, v, Kp, chunk, y0, ny, gc, s);
+        case P_FP32: return pack_chunk_impl<OutF32>(o, v, Kp, chunk, y0, ny, gc, s);
+        case P_BF16X3: return pack_chunk_impl<OutB3>(o, v, Kp, chunk, y0, ny, gc, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_pack(int prec, int o, int v, int Kp, const double* vvvo, const double* t2,
