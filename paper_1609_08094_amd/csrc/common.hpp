@@ -124,14 +124,18 @@ __host__ __device__ inline int64_t w_index(int a, int b, int c, int nb) {
 // work items in XCD-synchronous order).  17-18: direct-to-LDS staging with
 // larger workgroup tiles, 256x256 (2x2 waves of 128x128) and 256x128 (2x2
 // waves of 128x64), one workgroup per compute unit, fewer re-reads of shared
-// operand rows per flop.
+// operand rows per flop.  19-20: eight waves of 64x64 staging one copy of
+// the rows for a 256x128 (19) or 128x256 (20) tile, two waves per SIMD.
+// 21: 64x128 tiles (2x2 waves of 32x64), direct staging, three workgroups
+// per compute unit.
 struct TileCfg { int bm, bn, lds, nbat; };
-constexpr int NTILE_CFG = 19;
+constexpr int NTILE_CFG = 22;
 constexpr TileCfg TILE_CFGS[NTILE_CFG] = {
     {64, 64, 0, 1},   {128, 64, 0, 1},  {128, 128, 0, 1}, {128, 128, 1, 1}, {128, 256, 1, 1},
     {64, 128, 1, 1},  {128, 128, 2, 1}, {128, 256, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 2},
     {128, 128, 2, 2}, {128, 128, 2, 2}, {128, 128, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 1},
-    {128, 128, 2, 2}, {128, 128, 2, 1}, {256, 256, 2, 1}, {256, 128, 2, 1}};
+    {128, 128, 2, 2}, {128, 128, 2, 1}, {256, 256, 2, 1}, {256, 128, 2, 1},
+    {256, 128, 2, 1}, {128, 256, 2, 1}, {64, 128, 2, 1}};
 inline int tile_m(int cfg) { return TILE_CFGS[cfg].bm; }
 inline int tile_n(int cfg) { return TILE_CFGS[cfg].bn; }
 inline int tile_nbat(int cfg) { return TILE_CFGS[cfg].nbat; }

@@ -187,17 +187,17 @@ __global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ 
 // x 4 lane groups) and the staging writes (8 rows x 8 chunks per wave) are
 // free of bank conflicts.
 
-template <int WTM, int WTN, int ROWB>
-constexpr int lds_tile_bytes() { return 2 * (2 * WTM + 2 * WTN) * ROWB; }
+template <int WTM, int WTN, int ROWB, int WGM = 2, int WGN = 2>
+constexpr int lds_tile_bytes() { return 2 * (WGM * WTM + WGN * WTN) * ROWB; }
 
 // One (slot, pass, batch index, tile) work item of the LDS-staged kernel,
 // logical index `bid`, using the workgroup's LDS `lds`.  Every wave reaches
 // every barrier; on return all LDS traffic of the item has completed.
-template <class P, int WTM, int WTN, int ROWB, bool DIRECT>
+template <class P, int WTM, int WTN, int ROWB, bool DIRECT, int WGM = 2, int WGN = 2>
 __device__ __forceinline__ void lds_tile(const Slot* __restrict__ slots, int nslot, int bid, char* lds) {
     using E = typename P::E;
-    constexpr int NT = 256;
-    constexpr int BM = 2 * WTM, BN = 2 * WTN;
+    constexpr int NT = 64 * WGM * WGN;   // WGM x WGN waves of WTM x WTN
+    constexpr int BM = WGM * WTM, BN = WGN * WTN;
     constexpr int RS = ROWB;
     constexpr int ROWS = BM + BN;
     constexpr int TPR = ROWB / 16;
@@ -212,7 +212,7 @@ __device__ __forceinline__ void lds_tile(const Slot* __restrict__ slots, int nsl
     const int v = S->v, o = S->o, Kp = S->Kp;
     const int mt0 = tmi * BM, nt0 = tni * BN;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WGN, wn = wave % WGN;
     const int m0 = mt0 + wm * WTM, n0 = nt0 + wn * WTN;
     const int vm = max(0, min(MB, (v - m0 + 15) / 16));
     const int vn = max(0, min(NB, (v - n0 + 15) / 16));
@@ -335,6 +335,16 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
                                                                   int total) {
     __shared__ __attribute__((aligned(16))) char lds[lds_tile_bytes<WTM, WTN, ROWB>()];
     lds_tile<P, WTM, WTN, ROWB, DIRECT>(slots, nslot, xcd_remap(blockIdx.x, total), lds);
+}
+
+// Workgroups of WGM x WGN waves (more than 2 x 2): one staged copy of the
+// shared rows serves more waves, so the rows of G of one batch index are
+// read by fewer workgroups.
+template <class P, int WTM, int WTN, int WGM, int WGN, int MINB>
+__global__ __launch_bounds__(64 * WGM * WGN, MINB) void contract_lds_wide_kernel(const Slot* __restrict__ slots,
+                                                                                  int nslot, int total) {
+    __shared__ __attribute__((aligned(16))) char lds[lds_tile_bytes<WTM, WTN, 128, WGM, WGN>()];
+    lds_tile<P, WTM, WTN, 128, true, WGM, WGN>(slots, nslot, xcd_remap(blockIdx.x, total), lds);
 }
 
 // Persistent form: gridDim.x (a multiple of NXCD) resident workgroups walk the
@@ -831,6 +841,9 @@ static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int tot
         case 16: hipLaunchKernelGGL((contract_lds_persist_kernel<P, 64, 64, 128, 2, true>), dim3(persist_grid(2)), dim3(256), 0, s, d_slots, nslot, total); break;
         case 17: hipLaunchKernelGGL((contract_lds_kernel<P, 128, 128, 128, 1, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 18: hipLaunchKernelGGL((contract_lds_kernel<P, 128, 64, 128, 1, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 19: hipLaunchKernelGGL((contract_lds_wide_kernel<P, 64, 64, 4, 2, 2>), dim3(total), dim3(512), 0, s, d_slots, nslot, total); break;
+        case 20: hipLaunchKernelGGL((contract_lds_wide_kernel<P, 64, 64, 2, 4, 2>), dim3(total), dim3(512), 0, s, d_slots, nslot, total); break;
+        case 21: hipLaunchKernelGGL((contract_lds_kernel<P, 32, 64, 128, 3, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
