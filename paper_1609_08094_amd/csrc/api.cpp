@@ -529,7 +529,7 @@ int enqueue_pipeline(ccsdt_context* ctx, const Plan& P, int prec, hipStream_t s,
             continue;
         }
         LAUNCH(K_ENERGY, launch_energy(prec, d, n, ch.totE, part, s));
-        LAUNCH(K_REDUCE, launch_slot_reduce(d, n, 0, part, etrip, s));
+        LAUNCH(K_REDUCE, launch_slot_reduce(d, n, part, etrip, s));
     }
     return CCSDT_OK;
 }

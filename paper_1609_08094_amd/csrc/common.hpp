@@ -9,11 +9,12 @@ namespace ccsdt {
 
 // Packed operand rows are padded with zeros to a multiple of KPAD elements.
 constexpr int KPAD = 32;
-// W is stored in cubic blocks of WB^3 elements, block-major:
-//   W[(A*nb + B)*nb + C][a%WB][b%WB][c%WB],  A = a/WB, nb = ceil(v/WB),
-// so that a block of any index order is one contiguous read.  The energy
-// kernel walks orbits of these blocks (one per workgroup) and stages
-// SB^3 sub-blocks through LDS.
+// W is stored in cubic blocks of SB^3 elements, block-major:
+//   W[(A*2nb + B)*2nb + C][a%SB][b%SB][c%SB],  A = a/SB, nb = ceil(v/WB),
+// so that every SB^3 sub-block is one contiguous 2 KB (FP32) read.  The
+// energy kernel walks orbits of WB^3 blocks (one per workgroup) and stages
+// their SB^3 sub-blocks through LDS.  The buffer holds (2 nb)^3 SB^3 =
+// nb^3 WB^3 elements per pass.
 constexpr int WB = 16;
 constexpr int SB = 8;
 // Number of XCDs on MI355X; workgroups are dispatched round-robin over them.
@@ -72,8 +73,8 @@ hipError_t launch_contract(int prec, int tile_cfg, const Slot* d_slots, int nslo
 hipError_t launch_energy(int prec, const Slot* d_slots, int nslot, int total_wg,
                          double* partials, hipStream_t s);
 // Per-slot deterministic sum of partials into e_trip[trip_index].
-hipError_t launch_slot_reduce(const Slot* d_slots, int nslot, int norb_max_unused,
-                              const double* partials, double* e_trip, hipStream_t s);
+hipError_t launch_slot_reduce(const Slot* d_slots, int nslot, const double* partials, double* e_trip,
+                              hipStream_t s);
 // Per-problem deterministic sum of e_trip ranges into out[3*p].
 hipError_t launch_final_reduce(const int* d_trip_begin, int nprob, const double* e_trip,
                                double* out, hipStream_t s);
@@ -103,7 +104,8 @@ struct GapDesc {
 hipError_t launch_gap_check(const GapDesc* d_desc, int nprob, double* flag, hipStream_t s);
 
 __host__ __device__ inline int64_t w_index(int a, int b, int c, int nb) {
-    return ((((int64_t)(a >> 4) * nb + (b >> 4)) * nb + (c >> 4)) << 12) + ((a & 15) << 8) + ((b & 15) << 4) + (c & 15);
+    const int64_t n8 = 2 * (int64_t)nb;
+    return ((((int64_t)(a >> 3) * n8 + (b >> 3)) * n8 + (c >> 3)) << 9) + ((a & 7) << 6) + ((b & 7) << 3) + (c & 7);
 }
 
 // Contraction tile configurations (workgroup tile BM x BN over the (row, col)

@@ -12,7 +12,8 @@
 //
 // W = W_A + W_B.  The two passes are independent (one launch covers both),
 // each writes its own buffer once, and the energy kernel adds the two when
-// it stages W.  The three terms of a pass run as one K loop over three
+// it stages W.  For a triple taken as (p, p, q), W_B[a][b][c] = W_A[b][a][c]:
+// only pass A runs (Slot::npass = 1) and the energy kernel reads W_A twice.  The three terms of a pass run as one K loop over three
 // segments of length Kp.  W_A and W_B are FP64 for the FP64 path and FP32
 // otherwise, in the WB^3-blocked layout of common.hpp.
 //

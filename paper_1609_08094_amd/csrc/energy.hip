@@ -43,11 +43,31 @@ template <> struct Unpack<float> {
         d[2] = __uint_as_float(x.z) + __uint_as_float(y.z);
         d[3] = __uint_as_float(x.w) + __uint_as_float(y.w);
     }
+    static __device__ __forceinline__ void put1(float* d, u32x4 x) {
+        d[0] = __uint_as_float(x.x);
+        d[1] = __uint_as_float(x.y);
+        d[2] = __uint_as_float(x.z);
+        d[3] = __uint_as_float(x.w);
+    }
+    static __device__ __forceinline__ void add1(float* d, u32x4 y) {
+        d[0] += __uint_as_float(y.x);
+        d[1] += __uint_as_float(y.y);
+        d[2] += __uint_as_float(y.z);
+        d[3] += __uint_as_float(y.w);
+    }
 };
 template <> struct Unpack<double> {
     static __device__ __forceinline__ void put2(double* d, u32x4 x, u32x4 y) {
         d[0] = __hiloint2double((int)x.y, (int)x.x) + __hiloint2double((int)y.y, (int)y.x);
         d[1] = __hiloint2double((int)x.w, (int)x.z) + __hiloint2double((int)y.w, (int)y.z);
+    }
+    static __device__ __forceinline__ void put1(double* d, u32x4 x) {
+        d[0] = __hiloint2double((int)x.y, (int)x.x);
+        d[1] = __hiloint2double((int)x.w, (int)x.z);
+    }
+    static __device__ __forceinline__ void add1(double* d, u32x4 y) {
+        d[0] += __hiloint2double((int)y.y, (int)y.x);
+        d[1] += __hiloint2double((int)y.w, (int)y.z);
     }
 };
 
@@ -151,18 +171,22 @@ __global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict_
             // W sub-blocks, order q: (x,y,z) (x,z,y) (y,x,z) (y,z,x) (z,x,y) (z,y,x)
             const int P[6][3] = {{x, y, z}, {x, z, y}, {y, x, z}, {y, z, x}, {z, x, y}, {z, y, x}};
             u32x4 wa[6][NVL], wb[6][NVL];
+            // Each SB^3 sub-block is contiguous: load g of lane l covers
+            // elements VPR (l + 64 g) .. + VPR - 1, one coalesced 1 KB
+            // read per load across the wave.  Elements past v are never
+            // written by the contraction and never used here.
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
-                const int ga = min(SB * P[p][0] + r, v - 1), gb = min(SB * P[p][1] + cc, v - 1);
-                const int64_t off = w_index(ga, gb, SB * P[p][2], nb);
-                // one-pass slot (i = j): W_B[a][b][c] = W_A[b][a][c]
-                const int64_t offB = onepass ? w_index(gb, ga, SB * P[p][2], nb) : off;
+                const int64_t off = w_index(SB * P[p][0], SB * P[p][1], SB * P[p][2], nb);
+                // one-pass slot (i = j): W_B[a][b][c] = W_A[b][a][c], the sub-block
+                // with the first two indices exchanged
+                const int64_t offB = onepass ? w_index(SB * P[p][1], SB * P[p][0], SB * P[p][2], nb) : off;
                 const GLOBAL u32x4* srcA = (const GLOBAL u32x4*)(W + off);
                 const GLOBAL u32x4* srcB = (const GLOBAL u32x4*)((onepass ? W : WBp) + offB);
 #pragma unroll
                 for (int g = 0; g < NVL; ++g) {
-                    wa[p][g] = srcA[g];
-                    wb[p][g] = srcB[g];
+                    wa[p][g] = srcA[lane + 64 * g];
+                    wb[p][g] = srcB[lane + 64 * g];
                 }
             }
             // S sub-blocks: index pq*6 + qq, pairs qq: (y,z) (z,y) (x,z) (z,x) (x,y) (y,x)
@@ -190,10 +214,32 @@ __global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict_
                 }
                 tv[h] = val;
             }
+            if (!onepass) {
 #pragma unroll
-            for (int p = 0; p < 6; ++p)
+                for (int p = 0; p < 6; ++p)
 #pragma unroll
-                for (int g = 0; g < NVL; ++g) Unpack<WT>::put2(&L[p][r * PS + cc * RS + g * VPR], wa[p][g], wb[p][g]);
+                    for (int g = 0; g < NVL; ++g) {
+                        const int e = VPR * (lane + 64 * g);
+                        Unpack<WT>::put2(&L[p][(e >> 6) * PS + ((e >> 3) & 7) * RS + (e & 7)], wa[p][g], wb[p][g]);
+                    }
+            } else {
+                // W_A parts first, then W_B parts added at the exchanged positions
+#pragma unroll
+                for (int p = 0; p < 6; ++p)
+#pragma unroll
+                    for (int g = 0; g < NVL; ++g) {
+                        const int e = VPR * (lane + 64 * g);
+                        Unpack<WT>::put1(&L[p][(e >> 6) * PS + ((e >> 3) & 7) * RS + (e & 7)], wa[p][g]);
+                    }
+                wave_lds_fence();
+#pragma unroll
+                for (int p = 0; p < 6; ++p)
+#pragma unroll
+                    for (int g = 0; g < NVL; ++g) {
+                        const int e = VPR * (lane + 64 * g);
+                        Unpack<WT>::add1(&L[p][((e >> 3) & 7) * PS + (e >> 6) * RS + (e & 7)], wb[p][g]);
+                    }
+            }
 #pragma unroll
             for (int n = 0; n < 18; ++n) LS[n][r * SRS + cc] = sv[n];
             (&LT[0][0][0])[lane] = tv[0];
@@ -356,7 +402,7 @@ hipError_t launch_energy(int prec, const Slot* d_slots, int nslot, int total, do
     return hipGetLastError();
 }
 
-hipError_t launch_slot_reduce(const Slot* d_slots, int nslot, int, const double* partials, double* e_trip,
+hipError_t launch_slot_reduce(const Slot* d_slots, int nslot, const double* partials, double* e_trip,
                               hipStream_t s) {
     if (nslot <= 0) return hipSuccess;
     hipLaunchKernelGGL(slot_reduce_kernel, dim3(nslot), dim3(256), 0, s, d_slots, partials, e_trip);
