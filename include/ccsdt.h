@@ -214,11 +214,11 @@ int ccsdt_rimp2_pair_energies(ccsdt_context* ctx, const ccsdt_mp2_problem* prob,
 /* Flops of the pair products: o(o+1)/2 * 2 v^2 naux. */
 double ccsdt_rimp2_flops(int nocc, int nvirt, int naux);
 
-/* Tile plans.  The contraction kernel has NTILE = 22 tile configurations
+/* Tile plans.  The contraction kernel has NTILE = 25 tile configurations
  * (workgroup tile shape, operand staging through registers or LDS, direct
  * global-to-LDS loads, one or two batch indices per workgroup, fragment
- * prefetch, deep stage rings, persistent and eight-wave workgroups), numbered
- * 0..21.  The context keeps one choice per (precision, nvirt bucket), a
+ * prefetch, deep stage rings, persistent, paced persistent and eight-wave
+ * workgroups, 16x16 or 32x32 MFMA output blocks), numbered 0..24.  The context keeps one choice per (precision, nvirt bucket), a
  * bucket spanning nvirt in (2^(b-1), 2^b]; unset buckets use the built-in
  * default.  The environment variable CCSDT_TILE=<cfg> overrides every plan
  * (testing aid).

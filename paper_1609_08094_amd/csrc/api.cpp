@@ -94,6 +94,7 @@ struct ccsdt_context {
     // streaming of a host-resident vvvo: two device staging buffers, a copy
     // stream and the events that order copies and packs
     DevBuf stage;
+    DevBuf pace;                               // per-XCD counters of the paced contraction
     size_t stage_budget = 0;                   // CCSDT_STAGE_BYTES: both staging buffers together
     hipStream_t copy_stream = nullptr;
     hipEvent_t ev_copy[2] = {nullptr, nullptr}, ev_pack[2] = {nullptr, nullptr}, ev_start = nullptr;
@@ -101,7 +102,7 @@ struct ccsdt_context {
 
     size_t allocated() const {
         return gc.bytes + tc.bytes + w.bytes + part.bytes + etrip.bytes + slots.bytes + out.bytes + tripbeg.bytes +
-               pdesc.bytes + stage.bytes;
+               pdesc.bytes + stage.bytes + pace.bytes;
     }
 };
 
@@ -399,6 +400,7 @@ int plan_pipeline(ccsdt_context* ctx, Plan& P, int prec) {
     CHK(ensure(ctx, ctx->w, max_w, "W ring"));
     CHK(ensure(ctx, ctx->part, max_part, "energy partials"));
     CHK(ensure(ctx, ctx->slots, std::max<size_t>(P.trips.size(), 1) * sizeof(Slot), "slot table"));
+    CHK(ensure(ctx, ctx->pace, PACE_BYTES, "pacing counters"));
 
     P.slots.assign(P.trips.size(), Slot{});
     for (auto& ch : P.chunks) {
@@ -522,7 +524,7 @@ int enqueue_pipeline(ccsdt_context* ctx, const Plan& P, int prec, hipStream_t s,
     for (const auto& ch : P.chunks) {
         const Slot* d = dslots + ch.first;
         const int n = (int)ch.n;
-        LAUNCH(K_CONTRACT, launch_contract(prec, ch.cfg, d, n, ch.totA, s));
+        LAUNCH(K_CONTRACT, launch_contract(prec, ch.cfg, d, n, ch.totA, static_cast<unsigned*>(ctx->pace.p), s));
         if (debug_w) {
             const Slot& S = P.slots[ch.first];
             LAUNCH(K_REDUCE, launch_widen_w(prec, S.w, S.v, debug_w, s));
@@ -761,7 +763,7 @@ int ccsdt_context_destroy(ccsdt_context* ctx) {
         if (e) (void)hipEventDestroy(e);
     if (ctx->stage.p) (void)hipFree(ctx->stage.p);
     DevBuf* bufs[] = {&ctx->gc, &ctx->tc, &ctx->w, &ctx->part, &ctx->etrip, &ctx->slots, &ctx->out, &ctx->tripbeg,
-                      &ctx->pdesc};
+                      &ctx->pdesc, &ctx->pace};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->host_out) (void)hipHostFree(ctx->host_out);

@@ -67,8 +67,13 @@ hipError_t launch_pack_particle_chunk(int prec, int o, int v, int Kp, const doub
 // Particle part of G from density-fitting factors (see df.hip).
 hipError_t launch_assemble_df(int prec, int o, int v, int naux, int Kp, const double* bvv, const double* bvo,
                               void* gc, hipStream_t s);
-// Both contraction passes over the slots of a chunk (one launch).
-hipError_t launch_contract(int prec, int tile_cfg, const Slot* d_slots, int nslot, int total_wg, hipStream_t s);
+// Both contraction passes over the slots of a chunk (one launch).  `pace`
+// (PACE_BYTES of device memory) holds the per-workgroup progress counts of
+// the paced configuration (up to 2048 resident workgroups); the launch clears
+// them itself.
+constexpr size_t PACE_BYTES = 2048 * 128;
+hipError_t launch_contract(int prec, int tile_cfg, const Slot* d_slots, int nslot, int total_wg, unsigned* pace,
+                           hipStream_t s);
 // Energy partials over the block orbits of every slot.
 hipError_t launch_energy(int prec, const Slot* d_slots, int nslot, int total_wg,
                          double* partials, hipStream_t s);
@@ -129,15 +134,20 @@ __host__ __device__ inline int64_t w_index(int a, int b, int c, int nb) {
 // operand rows per flop.  19-20: eight waves of 64x64 staging one copy of
 // the rows for a 256x128 (19) or 128x256 (20) tile, two waves per SIMD.
 // 21: 64x128 tiles (2x2 waves of 32x64), direct staging, three workgroups
-// per compute unit.
+// per compute unit.  22-23: configurations 6 and 7 with 32x32 MFMA output
+// blocks (BF16X3 and FP32; FP64, which has no 32x32 MFMA, runs 6 and 7).
+// 24: configuration 16 with the workgroups of each XCD paced to within a few
+// K stages of each other, so that operand rows shared across tiles are still
+// in the XCD's L2 when the other tiles read them.
 struct TileCfg { int bm, bn, lds, nbat; };
-constexpr int NTILE_CFG = 22;
+constexpr int NTILE_CFG = 25;
 constexpr TileCfg TILE_CFGS[NTILE_CFG] = {
     {64, 64, 0, 1},   {128, 64, 0, 1},  {128, 128, 0, 1}, {128, 128, 1, 1}, {128, 256, 1, 1},
     {64, 128, 1, 1},  {128, 128, 2, 1}, {128, 256, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 2},
     {128, 128, 2, 2}, {128, 128, 2, 2}, {128, 128, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 1},
     {128, 128, 2, 2}, {128, 128, 2, 1}, {256, 256, 2, 1}, {256, 128, 2, 1},
-    {256, 128, 2, 1}, {128, 256, 2, 1}, {64, 128, 2, 1}};
+    {256, 128, 2, 1}, {128, 256, 2, 1}, {64, 128, 2, 1}, {128, 128, 2, 1}, {128, 256, 2, 1},
+    {128, 128, 2, 1}};
 inline int tile_m(int cfg) { return TILE_CFGS[cfg].bm; }
 inline int tile_n(int cfg) { return TILE_CFGS[cfg].bn; }
 inline int tile_nbat(int cfg) { return TILE_CFGS[cfg].nbat; }

@@ -72,10 +72,10 @@ __device__ __forceinline__ void store_tile(const Slot* S, int pass, int beta, in
 #pragma unroll
         for (int b = 0; b < WN; ++b) {
             if (a < vm && b < vn) {
-                const int n = n0 + b * 16 + (lane & 15);
+                const int n = n0 + b * P::BS + (lane % P::BS);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int m = m0 + a * 16 + P::out_row(lane, r);
+                for (int r = 0; r < P::NACC; ++r) {
+                    const int m = m0 + a * P::BS + P::out_row(lane, r);
                     if (m < v && n < v) {
                         // pass A: (a,b,c) = (beta, m, n); pass B: (m, beta, n)
                         const int64_t idx = pass ? w_index(m, beta, n, nb) : w_index(beta, m, n, nb);
@@ -191,11 +191,53 @@ __global__ __launch_bounds__(256) void contract_kernel(const Slot* __restrict__ 
 template <int WTM, int WTN, int ROWB, int WGM = 2, int WGN = 2>
 constexpr int lds_tile_bytes() { return 2 * (WGM * WTM + WGN * WTN) * ROWB; }
 
-// One (slot, pass, batch index, tile) work item of the LDS-staged kernel,
-// logical index `bid`, using the workgroup's LDS `lds`.  Every wave reaches
-// every barrier; on return all LDS traffic of the item has completed.
-template <class P, int WTM, int WTN, int ROWB, bool DIRECT, int WGM = 2, int WGN = 2>
-__device__ __forceinline__ void lds_tile(const Slot* __restrict__ slots, int nslot, int bid, char* lds) {
+// Bounded pacing of the workgroups of one XCD (contract_lds_paced_kernel).
+// Every PACE_PERIOD K stages a workgroup publishes how many stages it has
+// completed (a store to its own 128-byte line: no shared read-modify-write)
+// and then waits until every workgroup of its XCD has published at least
+// `lag` stages fewer, or has completed all of its work.  Workgroups reading
+// the same operand rows thus stay within a few stages of each other and find
+// the rows in the XCD's L2.  The wait only orders timing: a spin that exceeds
+// its bound switches pacing off for the workgroup, and no result depends on it.
+constexpr int PACE_PERIOD = 4;
+constexpr int PACE_SPIN_LIMIT = 4000;   // about 0.3 ms of s_sleep at the sustained clock
+constexpr int PACE_STRIDE = 32;         // unsigned ints per published count (128 bytes)
+
+struct Pacer {
+    unsigned* mine;        // this workgroup's published count
+    const unsigned* xcd;   // the XCD's counts, workgroup w at xcd[w * PACE_STRIDE]
+    int done;              // stages completed by this workgroup
+    int S;                 // stages per work item
+    int per, rem, tlo;     // workgroups of the XCD; item counts tlo + 1 (first rem) or tlo
+    int lag;
+    bool on;
+};
+
+__device__ __forceinline__ void pace_step(Pacer& pc) {
+    ++pc.done;
+    if (!pc.on || pc.done % PACE_PERIOD != 0 || threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    if (lane == 0) __hip_atomic_store(pc.mine, (unsigned)pc.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int c = pc.done - pc.lag;
+    if (c <= 0) return;
+    for (int spins = 0;; ++spins) {
+        bool ok = true;
+        for (int w = lane; w < pc.per; w += 64) {
+            const int need = min(c, (pc.tlo + (w < pc.rem ? 1 : 0)) * pc.S);
+            ok = ok && (int)__hip_atomic_load(pc.xcd + w * PACE_STRIDE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+        }
+        if (__all(ok)) return;
+        if (spins >= PACE_SPIN_LIMIT) {
+            pc.on = false;
+            return;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+template <class P, int WTM, int WTN, int ROWB, bool DIRECT, int WGM = 2, int WGN = 2, bool PACE = false>
+__device__ __forceinline__ void lds_tile(const Slot* __restrict__ slots, int nslot, int bid, char* lds,
+                                         Pacer* pc = nullptr) {
     using E = typename P::E;
     constexpr int NT = 64 * WGM * WGN;   // WGM x WGN waves of WTM x WTN
     constexpr int BM = WGM * WTM, BN = WGN * WTN;
@@ -205,7 +247,8 @@ __device__ __forceinline__ void lds_tile(const Slot* __restrict__ slots, int nsl
     constexpr int RPP = NT / TPR;
     constexpr int NP = ROWS / RPP;
     static_assert(ROWS % RPP == 0, "rows must split evenly over the threads");
-    constexpr int MB = WTM / 16, NB = WTN / 16;
+    constexpr int BS = P::BS;
+    constexpr int MB = WTM / BS, NB = WTN / BS;
     static_assert(ROWB == 128, "stage rows are eight 16-byte chunks");
 
     int pass, beta, tmi, tni;
@@ -215,8 +258,8 @@ __device__ __forceinline__ void lds_tile(const Slot* __restrict__ slots, int nsl
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wm = wave / WGN, wn = wave % WGN;
     const int m0 = mt0 + wm * WTM, n0 = nt0 + wn * WTN;
-    const int vm = max(0, min(MB, (v - m0 + 15) / 16));
-    const int vn = max(0, min(NB, (v - n0 + 15) / 16));
+    const int vm = max(0, min(MB, (v - m0 + BS - 1) / BS));
+    const int vn = max(0, min(NB, (v - n0 + BS - 1) / BS));
 
     const int64_t rowbytes = (int64_t)Kp * P::UNITS * sizeof(E);
     const int csteps = (int)(rowbytes / ROWB);
@@ -225,14 +268,14 @@ __device__ __forceinline__ void lds_tile(const Slot* __restrict__ slots, int nsl
     const char* T = static_cast<const char*>(S->tc);
     const int lrow = threadIdx.x / TPR, lcol = (threadIdx.x % TPR) * 16;
     // LDS chunk of this thread's staging chunk (RPP keeps the swizzle bits)
-    static_assert(RPP % 8 == 0, "staging rows must keep the swizzle bits");
+    static_assert(RPP % (BS == 32 ? 32 : 8) == 0, "staging rows must keep the swizzle bits");
     const int gch = lcol >> 4;
     const int lch = P::SPLIT ? ((gch & 1) * 4 + (gch >> 1)) : gch;
-    const int lcol_sw = (lch ^ lds_swz(lrow)) * 16;
+    const int lcol_sw = (lch ^ lds_swz_bs<BS>(lrow)) * 16;
     // Direct staging (global_load_lds): lane l of a wave's p-th load writes the
     // 16 bytes at LDS row lrow + p RPP, chunk l % 8; it fetches the global chunk
     // that belongs there under the same permutation and swizzle.
-    const int pch = (lane & 7) ^ lds_swz(lrow);
+    const int pch = (lane & 7) ^ lds_swz_bs<BS>(lrow);
     const int src_col = (P::SPLIT ? (((pch & 3) << 1) | (pch >> 2)) : pch) * 16;
     const int wave_row0 = (threadIdx.x >> 6) * (64 / TPR);
 
@@ -312,16 +355,17 @@ __device__ __forceinline__ void lds_tile(const Slot* __restrict__ slots, int nsl
         }
         __builtin_amdgcn_sched_barrier(0);
         if (active) {
-            const char* As = lds + buf * (ROWS * RS) + (wm * WTM + (lane & 15)) * RS;
-            const char* Bs = lds + buf * (ROWS * RS) + (BM + wn * WTN + (lane & 15)) * RS;
-            const int g = lane >> 4;
-            const int sw = lds_swz(lane & 15);
+            const char* As = lds + buf * (ROWS * RS) + (wm * WTM + (lane % BS)) * RS;
+            const char* Bs = lds + buf * (ROWS * RS) + (BM + wn * WTN + (lane % BS)) * RS;
+            const int g = lane / BS;
+            const int sw = lds_swz_bs<BS>(lane % BS);
             if (vm == MB && vn == NB)
                 lds_stage<P, MB, NB, RS, true>(acc, As, Bs, g, sw, vm, vn);
             else
                 lds_stage<P, MB, NB, RS, false>(acc, As, Bs, g, sw, vm, vn);
         }
         if constexpr (!DIRECT) CCSDT_LSTORE(buf ^ 1);
+        if constexpr (PACE) pace_step(*pc);
         lds_dma_barrier();
     }
 #undef CCSDT_SET_PTRS
@@ -363,6 +407,39 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_persist_kernel(const S
     const int q = total / NXCD, r = total % NXCD;
     const int begin = x * q + min(x, r), end = begin + q + (x < r ? 1 : 0);
     for (int id = begin + lw; id < end; id += per_xcd) lds_tile<P, WTM, WTN, ROWB, DIRECT>(slots, nslot, id, lds);
+}
+
+// Paced persistent form: the walk of contract_lds_persist_kernel with the
+// workgroups of each XCD held within `lag` K stages of each other (Pacer).
+// Pacing needs equal stage counts for all items (one Kp across the slots);
+// otherwise it stays off.  `pace` holds one count per workgroup at a
+// 128-byte stride, zero at launch.
+template <class P, int WTM, int WTN, int MINB>
+__global__ __launch_bounds__(256, MINB) void contract_lds_paced_kernel(const Slot* __restrict__ slots, int nslot,
+                                                                        int total, unsigned* pace, int lag) {
+    __shared__ __attribute__((aligned(16))) char lds[lds_tile_bytes<WTM, WTN, 128>()];
+    const int x = blockIdx.x % NXCD, lw = blockIdx.x / NXCD, per_xcd = gridDim.x / NXCD;
+    const int q = total / NXCD, r = total % NXCD;
+    const int begin = x * q + min(x, r), end = begin + q + (x < r ? 1 : 0);
+    const int Kp0 = slots[0].Kp;
+    bool uniform = true;
+    for (int s = 1; s < nslot; ++s) uniform = uniform && slots[s].Kp == Kp0;
+    Pacer pc;
+    pc.xcd = pace + (int64_t)x * per_xcd * PACE_STRIDE;
+    pc.mine = pace + ((int64_t)x * per_xcd + lw) * PACE_STRIDE;
+    pc.done = 0;
+    pc.S = NSEG * (int)((int64_t)Kp0 * P::UNITS * sizeof(typename P::E) / 128);
+    pc.per = per_xcd;
+    pc.tlo = (end - begin) / per_xcd;
+    pc.rem = (end - begin) % per_xcd;
+    pc.lag = lag;
+    pc.on = uniform && lag > 0;
+    for (int id = begin + lw; id < end; id += per_xcd)
+        lds_tile<P, WTM, WTN, 128, true, 2, 2, true>(slots, nslot, id, lds, &pc);
+}
+
+__global__ void pace_clear_kernel(unsigned* pace, int n) {
+    for (int w = threadIdx.x; w < n; w += blockDim.x) pace[w * PACE_STRIDE] = 0u;
 }
 
 // Batch-shared variant.  In every segment exactly one operand depends on the
@@ -820,8 +897,26 @@ static int persist_grid(int per_cu) {
     return (cus * per_cu + NXCD - 1) / NXCD * NXCD;
 }
 
+static int pace_lag() {
+    static int lag = -1;
+    if (lag < 0) {
+        const char* e = getenv("CCSDT_PACE_LAG");
+        lag = e ? atoi(e) : 2;
+        if (lag < 0) lag = 0;
+    }
+    return lag;
+}
+
 template <class P>
-static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int total, hipStream_t s) {
+static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int total, unsigned* pace, hipStream_t s) {
+    if (cfg == 24) {
+        const int grid = persist_grid(2);
+        if (!pace || (size_t)grid * PACE_STRIDE * sizeof(unsigned) > PACE_BYTES) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(pace_clear_kernel, dim3(1), dim3(256), 0, s, pace, grid);
+        hipLaunchKernelGGL((contract_lds_paced_kernel<P, 64, 64, 2>), dim3(grid), dim3(256), 0, s, d_slots, nslot,
+                           total, pace, pace_lag());
+        return hipGetLastError();
+    }
     switch (cfg) {
         case 0: hipLaunchKernelGGL((contract_kernel<P, 2, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 1: hipLaunchKernelGGL((contract_kernel<P, 4, 2>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
@@ -845,17 +940,20 @@ static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int tot
         case 19: hipLaunchKernelGGL((contract_lds_wide_kernel<P, 64, 64, 4, 2, 2>), dim3(total), dim3(512), 0, s, d_slots, nslot, total); break;
         case 20: hipLaunchKernelGGL((contract_lds_wide_kernel<P, 64, 64, 2, 4, 2>), dim3(total), dim3(512), 0, s, d_slots, nslot, total); break;
         case 21: hipLaunchKernelGGL((contract_lds_kernel<P, 32, 64, 128, 3, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 22: hipLaunchKernelGGL((contract_lds_kernel<typename Wide<P>::T, 64, 64, 128, 2, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 23: hipLaunchKernelGGL((contract_lds_kernel<typename Wide<P>::T, 64, 128, 128, 1, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_contract(int prec, int cfg, const Slot* d_slots, int nslot, int total, hipStream_t s) {
+hipError_t launch_contract(int prec, int cfg, const Slot* d_slots, int nslot, int total, unsigned* pace,
+                           hipStream_t s) {
     if (total <= 0) return hipSuccess;
     switch (prec) {
-        case P_FP64: return contract_impl<PrecF64>(cfg, d_slots, nslot, total, s);
-        case P_FP32: return contract_impl<PrecF32>(cfg, d_slots, nslot, total, s);
-        case P_BF16X3: return contract_impl<PrecB3>(cfg, d_slots, nslot, total, s);
+        case P_FP64: return contract_impl<PrecF64>(cfg, d_slots, nslot, total, pace, s);
+        case P_FP32: return contract_impl<PrecF32>(cfg, d_slots, nslot, total, pace, s);
+        case P_BF16X3: return contract_impl<PrecB3>(cfg, d_slots, nslot, total, pace, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -10,6 +10,12 @@
 // assignment, so the dot product covers every k exactly once.  Output: lane
 // l holds four rows of column l%16 -- rows l/16 + 4r for the FP64
 // instruction, 4(l/16) + r for the FP32-accumulating ones.
+//
+// The *W traits use 32x32 output blocks (v_mfma_f32_32x32x16_bf16,
+// v_mfma_f32_32x32x2_f32): the same flops per cycle from half as many
+// instructions, each reading half the operand registers per flop.  Lane l
+// supplies row l%32 and k-group l/32; it holds sixteen rows of column l%32,
+// rows 8(r/4) + 4(l/32) + r%4.
 #pragma once
 
 #include "common.hpp"
@@ -18,6 +24,7 @@ namespace ccsdt {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // HIP uint4 blocks scalar replacement
 
@@ -36,6 +43,8 @@ struct PrecF64 {
     static constexpr int KCH = 16;
     static constexpr int UNITS = 1;
     struct Frag { f64x4 x; };
+    static constexpr int BS = 16;     // output block edge
+    static constexpr int NACC = 4;    // accumulator elements per lane
     static __device__ __forceinline__ int out_row(int lane, int r) { return (lane >> 4) + 4 * r; }
     static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
         f.x = *reinterpret_cast<const GLOBAL f64x4*>(gp(row + c * 16 + 4 * (lane >> 4)));
@@ -69,6 +78,8 @@ struct PrecF32 {
     static constexpr int KCH = 16;
     static constexpr int UNITS = 1;
     struct Frag { f32x4 x; };
+    static constexpr int BS = 16;     // output block edge
+    static constexpr int NACC = 4;    // accumulator elements per lane
     static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
     static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
         f.x = *reinterpret_cast<const GLOBAL f32x4*>(gp(row + c * 16 + 4 * (lane >> 4)));
@@ -98,6 +109,8 @@ struct PrecB3 {
     static constexpr int KCH = 32;
     static constexpr int UNITS = 2;
     struct Frag { bf16x8 hi, lo; };
+    static constexpr int BS = 16;     // output block edge
+    static constexpr int NACC = 4;    // accumulator elements per lane
     static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
     static __device__ __forceinline__ void load(Frag& f, const E* row, int c, int lane) {
         const GLOBAL E* p = gp(row + (c * 4 + (lane >> 4)) * 16);
@@ -123,6 +136,61 @@ struct PrecB3 {
         mma_t<2>(acc, a, b);
     }
 };
+
+// PrecF32 with 32x32 output blocks.  A 128-byte stage row holds 32 k; sub-step
+// s, lane group g (0, 1) reads chunk 2 s + g, four k per lane, one per MFMA.
+struct PrecF32W : PrecF32 {
+    using Acc = f32x16;
+    static constexpr int BS = 32;
+    static constexpr int NACC = 16;
+    static __device__ __forceinline__ int out_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+    static constexpr int NSUB = 4;
+    static __device__ __forceinline__ void load_lds(Frag& f, const char* row, int g, int sub, int sw) {
+        f.x = *reinterpret_cast<const f32x4*>(row + 16 * ((2 * sub + g) ^ sw));
+    }
+    template <int T>
+    static __device__ __forceinline__ void mma_t(Acc& acc, const Frag& a, const Frag& b) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x[T], b.x[T], acc, 0, 0, 0);
+    }
+    static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
+        mma_t<0>(acc, a, b);
+        mma_t<1>(acc, a, b);
+        mma_t<2>(acc, a, b);
+        mma_t<3>(acc, a, b);
+    }
+};
+
+// PrecB3 with 32x32 output blocks.  A 128-byte stage row holds four groups of
+// 8 k; sub-step s, lane group g (0, 1) takes group q = 2 s + g (hi in LDS
+// chunk q, lo in chunk 4 + q).
+struct PrecB3W : PrecB3 {
+    using Acc = f32x16;
+    static constexpr int BS = 32;
+    static constexpr int NACC = 16;
+    static __device__ __forceinline__ int out_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+    static constexpr int NSUB = 2;
+    static __device__ __forceinline__ void load_lds(Frag& f, const char* row, int g, int sub, int sw) {
+        const int q = 2 * sub + g;
+        f.hi = *reinterpret_cast<const bf16x8*>(row + 16 * (q ^ sw));
+        f.lo = *reinterpret_cast<const bf16x8*>(row + 16 * ((4 + q) ^ sw));
+    }
+    template <int T>
+    static __device__ __forceinline__ void mma_t(Acc& acc, const Frag& a, const Frag& b) {
+        if constexpr (T == 0) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.lo, b.hi, acc, 0, 0, 0);
+        if constexpr (T == 1) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi, b.lo, acc, 0, 0, 0);
+        if constexpr (T == 2) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi, b.hi, acc, 0, 0, 0);
+    }
+    static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
+        mma_t<0>(acc, a, b);
+        mma_t<1>(acc, a, b);
+        mma_t<2>(acc, a, b);
+    }
+};
+
+// The 32x32-block form of a precision (FP64 has no 32x32 MFMA and keeps its own).
+template <class P> struct Wide { using T = P; };
+template <> struct Wide<PrecF32> { using T = PrecF32W; };
+template <> struct Wide<PrecB3> { using T = PrecB3W; };
 
 // BF16 split products with the lo*lo term kept (four MFMAs per chunk).  For
 // sums of squares (the diagonal RI-MP2 integrals g_aiai) the dropped lo*lo
@@ -160,6 +228,16 @@ __device__ __forceinline__ void lds_dma_barrier() {
 // (see the LDS-staged contraction kernel for the layout it serves).
 __device__ __forceinline__ int lds_swz(int row) { return (((row >> 1) & 1) << 2) | (((row >> 2) & 1) << 1); }
 
+// The swizzle for fragments of BS rows.  A 128-bit LDS read serves two
+// groups of eight lanes per cycle; for 32-row fragments (32x32 blocks) the
+// two groups read the same chunk of rows 16 apart, which lds_swz alone maps
+// to the same banks (measured: one conflict cycle per read).  Row bit 4 then
+// also flips chunk bit 0.
+template <int BS>
+__device__ __forceinline__ int lds_swz_bs(int row) {
+    return BS == 32 ? (lds_swz(row) ^ ((row >> 4) & 1)) : lds_swz(row);
+}
+
 // The MFMAs of one chunk for a wave's MB x NB blocks, product by product
 // across all blocks, so that consecutive MFMAs never feed each other (each
 // accumulator still sees its products in the order of P::mma).
@@ -181,13 +259,30 @@ __device__ __forceinline__ void mma_blocks(typename P::Acc (&acc)[MB][NB], const
 template <class P, int MB, int NB, int RS, bool FULL>
 __device__ __forceinline__ void lds_stage(typename P::Acc (&acc)[MB][NB], const char* As, const char* Bs, int g,
                                           int sw, int vm, int vn) {
+    if constexpr (P::BS == 32) {
+        // 32x32 blocks: the fragments of every sub-step are read before the
+        // stage's first MFMA (as many registers as one 16x16 sub-step), so
+        // the LDS latency is exposed once per stage, not once per sub-step.
+        typename P::Frag fa[P::NSUB][MB], fb[P::NSUB][NB];
+#pragma unroll
+        for (int sub = 0; sub < P::NSUB; ++sub) {
+#pragma unroll
+            for (int a = 0; a < MB; ++a) P::load_lds(fa[sub][a], As + a * P::BS * RS, g, sub, sw);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) P::load_lds(fb[sub][b], Bs + b * P::BS * RS, g, sub, sw);
+        }
+#pragma unroll
+        for (int sub = 0; sub < P::NSUB; ++sub)
+            mma_blocks<P, MB, NB, FULL>(acc, fa[sub], fb[sub], vm, vn);
+        return;
+    }
 #pragma unroll
     for (int sub = 0; sub < P::NSUB; ++sub) {
         typename P::Frag fa[MB], fb[NB];
 #pragma unroll
-        for (int a = 0; a < MB; ++a) P::load_lds(fa[a], As + a * 16 * RS, g, sub, sw);
+        for (int a = 0; a < MB; ++a) P::load_lds(fa[a], As + a * P::BS * RS, g, sub, sw);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) P::load_lds(fb[b], Bs + b * 16 * RS, g, sub, sw);
+        for (int b = 0; b < NB; ++b) P::load_lds(fb[b], Bs + b * P::BS * RS, g, sub, sw);
 #pragma unroll
         for (int a = 0; a < MB; ++a)
 #pragma unroll
@@ -206,9 +301,9 @@ __device__ __forceinline__ void lds_stage_pm(typename P::Acc (&acc)[MB][NB], con
     for (int sub = 0; sub < P::NSUB; ++sub) {
         typename P::Frag fa[MB], fb[NB];
 #pragma unroll
-        for (int a = 0; a < MB; ++a) P::load_lds(fa[a], As + a * 16 * RS, g, sub, sw);
+        for (int a = 0; a < MB; ++a) P::load_lds(fa[a], As + a * P::BS * RS, g, sub, sw);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) P::load_lds(fb[b], Bs + b * 16 * RS, g, sub, sw);
+        for (int b = 0; b < NB; ++b) P::load_lds(fb[b], Bs + b * P::BS * RS, g, sub, sw);
         mma_blocks<P, MB, NB, FULL>(acc, fa, fb, vm, vn);
     }
 }

@@ -170,7 +170,7 @@ def tile_cases():
     return cases
 
 
-@pytest.mark.parametrize("cfg", list(range(22)))
+@pytest.mark.parametrize("cfg", list(range(25)))
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_every_tile_config(ctx, tile_cases, cfg, prec, monkeypatch):
     monkeypatch.setenv("CCSDT_TILE", str(cfg))
@@ -215,7 +215,7 @@ def test_tile_configs_agree_at_hbm_scale(ctx, hbm_case, monkeypatch):
     o_ref = T.triple_restricted(i, j, k, host["eps_o"], host["eps_v"], host["t1"], host["t2"], vv,
                                 host["ovoo"], host["ovov"])
     assert abs(ref[0][0] - o_ref[0]) <= 1e-10 * abs(o_ref[1])
-    for cfg in range(1, 22):
+    for cfg in range(1, 25):
         monkeypatch.setenv("CCSDT_TILE", str(cfg))
         for prec in ("fp64", "fp32", "bf16x3"):
             say(f"hbm scale cfg {cfg} {prec}")
