@@ -55,6 +55,38 @@ def measured_traffic(key):
     return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
 
 
+def blas_reference():
+    """Vendor-library BF16 rates on this device (random N(0,1) operands, FP32
+    accumulation, contiguous operands): square products, and batched products
+    of the shape of one contraction pass at C3 (v x v outputs, K = Kp)."""
+    import torch
+    torch.manual_seed(0)
+
+    def rate(fn, flops, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return flops * reps / (time.perf_counter() - t0) / 1e12
+
+    out = {}
+    for n in (4096, 8192, 16384):
+        a = torch.randn(n, n, device="cuda", dtype=torch.bfloat16)
+        b = torch.randn(n, n, device="cuda", dtype=torch.bfloat16)
+        out[f"matmul {n}x{n}x{n}"] = rate(lambda: a @ b, 2.0 * n ** 3)
+        log(f"blas reference: square {n} done")
+        del a, b
+    for (bt, m, n, k) in [(600, 600, 600, 640), (300, 1200, 600, 640), (64, 4800, 600, 640)]:
+        a = torch.randn(bt, m, k, device="cuda", dtype=torch.bfloat16)
+        b = torch.randn(bt, k, n, device="cuda", dtype=torch.bfloat16)
+        out[f"bmm {bt}x({m}x{k})x({k}x{n})"] = rate(lambda: torch.bmm(a, b), 2.0 * bt * m * n * k)
+        log(f"blas reference: batched {bt} done")
+        del a, b
+    print(json.dumps({"blas_reference_tflops": out, "peak_bf16_tflops": 2500.0}), flush=True)
+
+
 def triple_flops(o, v, m):
     return m * (2.0 * v ** 4 + 2.0 * o * v ** 3)
 
@@ -133,10 +165,16 @@ def main():
     ap.add_argument("--partial-triples", type=int, default=0, metavar="N",
                     help="profiling aid: instead of a step, evaluate the N distinct triples (0, 1, 2..N+1) "
                          "twice (kernel loading, then the run to profile) and print their kernel times")
+    ap.add_argument("--blas-reference", action="store_true",
+                    help="only time torch.matmul / torch.bmm in bf16 (hipBLASLt) on large square and on "
+                         "contraction-shaped batched products, as a reference rate for the MFMA peak, and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device to device five times (reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.blas_reference:
+        blas_reference()
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 4
