@@ -165,6 +165,9 @@ def main():
     ap.add_argument("--partial-triples", type=int, default=0, metavar="N",
                     help="profiling aid: instead of a step, evaluate the N distinct triples (0, 1, 2..N+1) "
                          "twice (kernel loading, then the run to profile) and print their kernel times")
+    ap.add_argument("--vs-fp64", action="store_true",
+                    help="after the timed steps, run one full step in FP64 (outside the timed region) and "
+                         "report its time, the energy difference and the speedup")
     ap.add_argument("--blas-reference", action="store_true",
                     help="only time torch.matmul / torch.bmm in bf16 (hipBLASLt) on large square and on "
                          "contraction-shaped batched products, as a reference rate for the MFMA peak, and exit")
@@ -269,6 +272,18 @@ def main():
             and not os.environ.get("CCSDT_TILE"):
         traffic = measured_traffic("contract_lds_kernel<PrecB3,64,64,128,2,true>|C3")
 
+    vs64 = None
+    if args.vs_fp64 and args.precision != "fp64":
+        log("bench: one full FP64 step for comparison (not timed as a step)")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E64, E4_64, E5_64 = energy(ctx, dev, "fp64", stream)
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - t0) * 1e3
+        vs64 = {"fp64_ms_per_step": ms64, "E_fp64": E64, "dE": E - E64,
+                "rel_dE": abs(E - E64) / abs(E64), "speedup_vs_fp64": ms64 / ms,
+                "within_1e-6": abs(E - E64) <= 1e-6 * max(1.0, abs(E64))}
+
     sample = [tuple(int(x) for x in s.split(",")) for s in args.sample.split(";") if s]
     parity = None
     cpu = None
@@ -310,6 +325,8 @@ def main():
         "parity_sample": parity,
         "cpu_baseline": cpu,
     }
+    if vs64 is not None:
+        line["vs_fp64"] = vs64
     print(json.dumps(line), flush=True)
     ctx.close()
 
