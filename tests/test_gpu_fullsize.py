@@ -1,0 +1,83 @@
+"""Parity at the full C3 size (o=40, v=600), in the launch configuration the
+benchmark times: the default tile plan and chunks of two triples under the
+default W budget, packed operands of the whole problem in HBM.
+
+The oracle evaluates sampled triples one by one on the host (about half a
+minute each at this size); every sampled triple is also compared across the
+three precisions.  (3, 3, 17) has two equal indices and runs the one-pass
+contraction.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_08094_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TRIPS = [(0, 1, 2), (3, 3, 17), (5, 20, 39), (38, 39, 39)]
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1609_08094_amd import ccsdt
+    ccsdt.load_library()
+    cfg = synth.CONFIGS["C3"]
+    say("generating C3 inputs on the GPU")
+    d = synth.make_problem_device(cfg["o"], cfg["v"], seed=0, device="cuda")
+    torch.cuda.synchronize()
+    ctx = ccsdt.Context()
+    assert ctx.plan_get("bf16x3", cfg["v"]) == 6 and ctx.plan_get("fp64", cfg["v"]) == 6
+    res = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        say(f"C3 sampled triples {TRIPS} {prec}")
+        res[prec] = ctx.triple_energies(d, TRIPS, prec)
+    ctx.close()
+    yield d, res
+    del d
+    torch.cuda.empty_cache()
+
+
+class _Slices:
+    """vvvo[..., q] for the occupied indices of one triple, on the host."""
+
+    def __init__(self, vvvo, qs):
+        self.s = {q: np.ascontiguousarray(vvvo[..., q].cpu().numpy()) for q in qs}
+
+    def __getitem__(self, key):
+        return self.s[key[-1]]
+
+
+def _oracle_triple(d, t):
+    host = {f: d[f].cpu().numpy() for f in ("eps_o", "eps_v", "t1", "t2", "ovoo", "ovov")}
+    vv = _Slices(d["vvvo"], sorted(set(t)))
+    say(f"oracle triple {t} (host)")
+    return oracle.triple_restricted(*t, host["eps_o"], host["eps_v"], host["t1"], host["t2"], vv,
+                                    host["ovoo"], host["ovov"])
+
+
+@pytest.mark.parametrize("n", [0, 1])
+def test_c3_fp64_triple_against_oracle(c3, n):
+    d, res = c3
+    t = TRIPS[n]
+    ref = _oracle_triple(d, t)
+    got = res["fp64"][n]
+    assert abs(got[0] - ref[0]) <= 1e-10 * abs(ref[1]), (t, got, ref)
+    assert abs(got[2] - ref[2]) <= 1e-10 * abs(ref[1]), (t, got, ref)
+
+
+def test_c3_mixed_precisions_against_fp64(c3):
+    d, res = c3
+    for prec in ("fp32", "bf16x3"):
+        for t, g, r in zip(TRIPS, res[prec], res["fp64"]):
+            assert abs(g[0] - r[0]) <= 1e-6 * max(1.0, abs(r[0])), (prec, t, g, r)
+    # the triples carry different energies (no slot was skipped or duplicated)
+    assert len({round(r[0], 3) for r in res["fp64"]}) == len(TRIPS)
