@@ -192,19 +192,29 @@ template <class P> struct Wide { using T = P; };
 template <> struct Wide<PrecF32> { using T = PrecF32W; };
 template <> struct Wide<PrecB3> { using T = PrecB3W; };
 
-// BF16 split products with the lo*lo term kept (four MFMAs per chunk).  For
-// sums of squares (the diagonal RI-MP2 integrals g_aiai) the dropped lo*lo
-// term of PrecB3 is a one-signed bias of about 2^-16 relative; with it the
-// remaining error is the signed residual of the two-term split and the FP32
-// accumulation.
+// BF16 split products with the lo*lo term kept (four MFMAs per chunk), into
+// two FP32 accumulators: hi*hi in `big`, the three correction products in
+// `small`, added when read.  For sums of squares (the diagonal RI-MP2
+// integrals g_aiai) the dropped lo*lo term of PrecB3 is a one-signed bias of
+// about 2^-16 relative; kept in the same accumulator as hi*hi it would still
+// be lost, since each chunk's lo*lo sum lies below half an ulp of the
+// accumulated hi*hi sum.  In a separate accumulator, which stays small, it
+// survives; the remaining error is the signed residual of the two-term split
+// and the FP32 accumulation.
+struct AccPair {
+    f32x4 big, small;
+    __device__ __forceinline__ float operator[](int r) const { return big[r] + small[r]; }
+};
+
 struct PrecB4 : PrecB3 {
+    using Acc = AccPair;
     static constexpr int NMMA = 4;
     template <int T>
     static __device__ __forceinline__ void mma_t(Acc& acc, const Frag& a, const Frag& b) {
-        if constexpr (T == 0) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.lo, acc, 0, 0, 0);
-        if constexpr (T == 1) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
-        if constexpr (T == 2) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc, 0, 0, 0);
-        if constexpr (T == 3) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc, 0, 0, 0);
+        if constexpr (T == 0) acc.small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.lo, acc.small, 0, 0, 0);
+        if constexpr (T == 1) acc.small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc.small, 0, 0, 0);
+        if constexpr (T == 2) acc.small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc.small, 0, 0, 0);
+        if constexpr (T == 3) acc.big = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc.big, 0, 0, 0);
     }
     static __device__ __forceinline__ void mma(Acc& acc, const Frag& a, const Frag& b) {
         mma_t<0>(acc, a, b);

@@ -8,7 +8,8 @@
 // pair energy e_ij = - sum_ab G(2G - G^T)/D is symmetric in (i, j).  The
 // library forms G_ij for i <= j (one batched NT product per chunk of pairs on
 // MFMA: FP64, FP32, or the BF16 split with all four hi/lo products, since the
-// diagonal g_aiai are sums of squares) into a pair buffer; then an FP64
+// diagonal g_aiai are sums of squares, the three correction products in an
+// accumulator of their own) into a pair buffer; then an FP64
 // energy kernel reads each 64 x 64 block of G_ij together with its transposed
 // partner, and E = sum_i e_ii + 2 sum_{i<j} e_ij is summed in a fixed order.
 #include "common.hpp"

@@ -81,3 +81,41 @@ def test_c3_mixed_precisions_against_fp64(c3):
             assert abs(g[0] - r[0]) <= 1e-6 * max(1.0, abs(r[0])), (prec, t, g, r)
     # the triples carry different energies (no slot was skipped or duplicated)
     assert len({round(r[0], 3) for r in res["fp64"]}) == len(TRIPS)
+
+
+# ---------------------------------------------------------------- RI-MP2 at M1
+PAIRS = [(0, 0), (0, 1), (59, 118), (118, 118)]
+
+
+@pytest.fixture(scope="module")
+def m1():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1609_08094_amd import ccsdt
+    cfg = synth.MP2_CONFIGS["M1"]
+    say("generating M1 inputs on the GPU")
+    d = synth.make_mp2_problem(cfg["o"], cfg["v"], cfg["naux"], seed=0, device="cuda")
+    torch.cuda.synchronize()
+    ctx = ccsdt.Context()
+    res = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        say(f"M1 sampled pairs {PAIRS} {prec}")
+        res[prec] = ctx.rimp2_pair_energies(d, PAIRS, prec)
+    ctx.close()
+    yield d, res
+    del d
+    torch.cuda.empty_cache()
+
+
+def test_m1_pairs_against_oracle(m1):
+    """RI-MP2 pair energies at the full M1 size (o=119, v=2546, naux=5852),
+    diagonal and off-diagonal pairs, against the oracle's pair energy."""
+    d, res = m1
+    eo, ev = d["eps_o"].cpu().numpy(), d["eps_v"].cpu().numpy()
+    rows = {i: d["c_ov"][i].cpu().numpy() for t in PAIRS for i in t}
+    for n, (i, j) in enumerate(PAIRS):
+        say(f"oracle pair ({i}, {j})")
+        ref = oracle.rimp2_pair_energy(i, j, eo, ev, rows)
+        assert abs(res["fp64"][n] - ref) <= 1e-10 * abs(ref), (i, j, res["fp64"][n], ref)
+        for prec in ("fp32", "bf16x3"):
+            assert abs(res[prec][n] - ref) <= 1e-6 * abs(ref), (prec, i, j, res[prec][n], ref)
