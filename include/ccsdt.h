@@ -106,7 +106,8 @@ typedef struct ccsdt_problem {
 /* Opaque handle that keeps device workspace (packed operands, the W ring,
  * partial sums), the tile plan cache and captured graphs between calls.  A
  * context is bound to the device current at creation and must be used by
- * one thread at a time. */
+ * one thread at a time; a call that launches work while another device is
+ * current fails with CCSDT_EINVAL. */
 typedef struct ccsdt_context ccsdt_context;
 
 int ccsdt_context_create(ccsdt_context** ctx_out);

@@ -275,6 +275,18 @@ int check_gap(const ccsdt_problem* p, hipStream_t s, int idx) {
     return CCSDT_OK;
 }
 
+// A context owns device memory of the device that was current when it was
+// created; a call that launches work must run with that device current.
+int check_ctx(ccsdt_context* ctx) {
+    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != ctx->device)
+        return fail(CCSDT_EINVAL, "context belongs to device " + std::to_string(ctx->device) +
+                                      ", but device " + std::to_string(dev) + " is current");
+    return CCSDT_OK;
+}
+
 int check_prec(int prec) {
     if (prec != CCSDT_FP64 && prec != CCSDT_FP32 && prec != CCSDT_BF16X3)
         return fail(CCSDT_EUNSUPPORTED, "unknown precision " + std::to_string(prec));
@@ -820,7 +832,7 @@ static int eager_energy(ccsdt_context* ctx, Plan& P, const std::vector<int>& tb,
 
 static int energy_many(ccsdt_context* ctx, int nprob, const ccsdt_problem* probs, int prec, void* stream,
                        double* out_host) {
-    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    CHK(check_ctx(ctx));
     if (!out_host) return fail(CCSDT_EINVAL, "null output");
     if (nprob < 1 || !probs) return fail(CCSDT_EINVAL, "no problems");
     CHK(check_prec(prec));
@@ -863,7 +875,7 @@ int ccsdt_energy(ccsdt_context* ctx, const ccsdt_problem* prob, int precision, v
 
 int ccsdt_energy_df(ccsdt_context* ctx, const ccsdt_problem_df* prob, int precision, void* hip_stream,
                     double* out_host) {
-    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    CHK(check_ctx(ctx));
     if (!out_host) return fail(CCSDT_EINVAL, "null output");
     CHK(check_prec(precision));
     ProbLayout L;
@@ -930,7 +942,7 @@ static int triple_energies_impl(ccsdt_context* ctx, const ProbLayout& L, int pre
 
 int ccsdt_triple_energies(ccsdt_context* ctx, const ccsdt_problem* prob, int precision, int ntrip,
                           const int* ijk_host, void* hip_stream, double* out_host) {
-    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    CHK(check_ctx(ctx));
     if (!out_host || !ijk_host) return fail(CCSDT_EINVAL, "null argument");
     if (ntrip < 1) return fail(CCSDT_EINVAL, "ntrip must be >= 1");
     CHK(check_prec(precision));
@@ -943,7 +955,7 @@ int ccsdt_triple_energies(ccsdt_context* ctx, const ccsdt_problem* prob, int pre
 
 int ccsdt_triple_energies_df(ccsdt_context* ctx, const ccsdt_problem_df* prob, int precision, int ntrip,
                              const int* ijk_host, void* hip_stream, double* out_host) {
-    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    CHK(check_ctx(ctx));
     if (!out_host || !ijk_host) return fail(CCSDT_EINVAL, "null argument");
     if (ntrip < 1) return fail(CCSDT_EINVAL, "ntrip must be >= 1");
     CHK(check_prec(precision));
@@ -954,7 +966,7 @@ int ccsdt_triple_energies_df(ccsdt_context* ctx, const ccsdt_problem_df* prob, i
 
 int ccsdt_debug_w(ccsdt_context* ctx, const ccsdt_problem* prob, int precision, int i, int j, int k,
                   void* hip_stream, double* w_host) {
-    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    CHK(check_ctx(ctx));
     if (!w_host) return fail(CCSDT_EINVAL, "null w_host");
     CHK(check_prec(precision));
     CHK(check_problem(prob, -1));
@@ -994,7 +1006,7 @@ int ccsdt_debug_w(ccsdt_context* ctx, const ccsdt_problem* prob, int precision, 
 }
 
 int ccsdt_autotune(ccsdt_context* ctx, const ccsdt_problem* prob, int precision, void* hip_stream, int* cfg_out) {
-    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    CHK(check_ctx(ctx));
     CHK(check_prec(precision));
     CHK(check_problem(prob, -1));
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -1110,7 +1122,7 @@ static int mp2_run(ccsdt_context* ctx, const ccsdt_mp2_problem* p, int prec, con
 
 int ccsdt_rimp2_energy(ccsdt_context* ctx, const ccsdt_mp2_problem* prob, int precision, void* hip_stream,
                        double* e_out) {
-    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    CHK(check_ctx(ctx));
     if (!e_out) return fail(CCSDT_EINVAL, "null output");
     CHK(check_prec(precision));
     CHK(mp2_check(prob));
@@ -1132,7 +1144,7 @@ int ccsdt_rimp2_energy(ccsdt_context* ctx, const ccsdt_mp2_problem* prob, int pr
 
 int ccsdt_rimp2_pair_energies(ccsdt_context* ctx, const ccsdt_mp2_problem* prob, int precision, int npair,
                               const int* ij_host, void* hip_stream, double* out_host) {
-    if (!ctx) return fail(CCSDT_EINVAL, "null context");
+    CHK(check_ctx(ctx));
     if (!out_host || !ij_host) return fail(CCSDT_EINVAL, "null argument");
     if (npair < 1) return fail(CCSDT_EINVAL, "npair must be >= 1");
     CHK(check_prec(precision));
