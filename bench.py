@@ -266,6 +266,15 @@ def main():
     achieved = mf * flops_a_per_launch / (avg_a * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     kernels = {k: {"launches": n // max(args.steps, 1), "ms_per_step": t / args.steps} for k, (n, t) in prof.items()}
+    # energy kernel (HBM-bound): algorithmic bytes per triple = W_A + W_B read
+    # once (2 v^3 elements of W) plus the three v x v FP64 integral slices
+    ne, ms_e = prof["energy"]
+    ntrip = o * (o + 1) * (o + 2) // 6 - o
+    e_bytes = args.steps * ntrip * (2.0 * v ** 3 * (8 if args.precision == "fp64" else 4) + 3.0 * v * v * 8)
+    e_gbs = e_bytes / (ms_e * 1e-3) / 1e9 if ms_e > 0 else 0.0
+    energy_roofline = {"bound": "hbm", "achieved": e_gbs, "peak": 8000.0, "unit": "GB/s", "frac": e_gbs / 8000.0,
+                       "kernel": "energy", "avg_launch_ms": ms_e / max(ne, 1),
+                       "bytes_per_triple": e_bytes / max(args.steps * ntrip, 1)}
     # traffic (bytes per launch) was measured for the default plan of C3 BF16x3
     traffic = None
     if args.config == "C3" and args.precision == "bf16x3" and not df and ctx.plan_get(args.precision, v) == 6 \
@@ -321,6 +330,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": "contraction", "avg_launch_ms": avg_a, "launches_per_step": na // args.steps},
+        "energy_roofline": energy_roofline,
         "kernels": kernels,
         "parity_sample": parity,
         "cpu_baseline": cpu,
@@ -386,6 +396,15 @@ def bench_mp2(args, torch, ccsdt, synth):
                "sample": f"{len(sample)} pair energies {sample} of RI-MP2 {args.config}, {fl:.3e} flops "
                          f"(pair products counted once) in {dt:.1f}s"}
     kernels = {k: {"launches": n // max(args.steps, 1), "ms_per_step": t / args.steps} for k, (n, t) in prof.items()}
+    # energy kernel (HBM-bound): algorithmic bytes per triple = W_A + W_B read
+    # once (2 v^3 elements of W) plus the three v x v FP64 integral slices
+    ne, ms_e = prof["energy"]
+    ntrip = o * (o + 1) * (o + 2) // 6 - o
+    e_bytes = args.steps * ntrip * (2.0 * v ** 3 * (8 if args.precision == "fp64" else 4) + 3.0 * v * v * 8)
+    e_gbs = e_bytes / (ms_e * 1e-3) / 1e9 if ms_e > 0 else 0.0
+    energy_roofline = {"bound": "hbm", "achieved": e_gbs, "peak": 8000.0, "unit": "GB/s", "frac": e_gbs / 8000.0,
+                       "kernel": "energy", "avg_launch_ms": ms_e / max(ne, 1),
+                       "bytes_per_triple": e_bytes / max(args.steps * ntrip, 1)}
     line = {
         "metric": "RI-MP2 GFLOP/s & MFMA util (pair products o(o+1)/2 * 2 v^2 naux)",
         "value": F / (ms * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
