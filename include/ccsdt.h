@@ -221,10 +221,11 @@ double ccsdt_rimp2_flops(int nocc, int nvirt, int naux);
  * prefetch, deep stage rings, persistent, paced persistent and eight-wave
  * workgroups, 16x16 or 32x32 MFMA output blocks), numbered 0..24.  The
  * context keeps one choice per (precision, nvirt bucket), a bucket spanning
- * nvirt in (2^(b-1), 2^b]; unset buckets use the built-in default.  The environment variable CCSDT_TILE=<cfg> overrides every plan
- * (testing aid); CCSDT_PACE_LAG=<n> sets how many K stages the workgroups of
- * one XCD may drift apart in configuration 24 (default 2, 0 = unpaced), read
- * once per process.
+ * nvirt in (2^(b-1), 2^b]; unset buckets use the built-in default.  The
+ * environment variable CCSDT_TILE=<cfg> overrides every plan (testing aid);
+ * CCSDT_PACE_LAG=<n> sets how many K stages the workgroups of one XCD may
+ * drift apart in configuration 24 (default 2, 0 = unpaced), read once per
+ * process.
  *
  * ccsdt_autotune times the contraction of every configuration on up to four
  * triples of ``prob`` (each twice, the second run counted) and stores the

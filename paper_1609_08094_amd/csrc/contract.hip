@@ -13,9 +13,10 @@
 // W = W_A + W_B.  The two passes are independent (one launch covers both),
 // each writes its own buffer once, and the energy kernel adds the two when
 // it stages W.  For a triple taken as (p, p, q), W_B[a][b][c] = W_A[b][a][c]:
-// only pass A runs (Slot::npass = 1) and the energy kernel reads W_A twice.  The three terms of a pass run as one K loop over three
-// segments of length Kp.  W_A and W_B are FP64 for the FP64 path and FP32
-// otherwise, in the WB^3-blocked layout of common.hpp.
+// only pass A runs (Slot::npass = 1) and the energy kernel reads W_A twice.
+// The three terms of a pass run as one K loop over three segments of length
+// Kp.  W_A and W_B are FP64 for the FP64 path and FP32 otherwise, in the
+// SB^3-blocked layout of common.hpp.
 //
 // MFMA shapes (all with a 16x16 output block; lane l holds four rows of
 // column l%16: rows l/16 + 4r for the FP64 instruction, 4(l/16) + r for the
