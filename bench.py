@@ -166,8 +166,11 @@ def main():
                     help="profiling aid: instead of a step, evaluate the N distinct triples (0, 1, 2..N+1) "
                          "twice (kernel loading, then the run to profile) and print their kernel times")
     ap.add_argument("--vs-fp64", action="store_true",
-                    help="after the timed steps, run one full step in FP64 (outside the timed region) and "
-                         "report its time, the energy difference and the speedup")
+                    help="after the timed steps, evaluate the whole problem in FP64 (outside the timed "
+                         "region, over slices of about 1500 triples) and report its time, the energy "
+                         "difference and the speedup")
+    ap.add_argument("--vs-fp32", action="store_true",
+                    help="with --vs-fp64: also evaluate the whole problem in FP32 the same way")
     ap.add_argument("--blas-reference", action="store_true",
                     help="only time torch.matmul / torch.bmm in bf16 (hipBLASLt) on large square and on "
                          "contraction-shaped batched products, as a reference rate for the MFMA peak, and exit")
@@ -281,17 +284,35 @@ def main():
             and not os.environ.get("CCSDT_TILE"):
         traffic = measured_traffic("contract_lds_kernel<PrecB3,64,64,128,2,true>|C3")
 
+    def sliced(prec):
+        """Whole-problem energy in another precision over slices of the triple
+        list (each call packs the operands once), summed exactly; (E, ms, n)."""
+        import math
+        allt = [(i, j, k) for i in range(o) for j in range(i, o) for k in range(j, o) if not (i == j == k)]
+        nsl = max(1, -(-len(allt) // 1500))
+        per = -(-len(allt) // nsl)
+        parts, msum = [], 0.0
+        for n in range(nsl):
+            sl = allt[n * per:(n + 1) * per]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            parts += triples(dev, sl, prec, stream)
+            torch.cuda.synchronize()
+            msum += (time.perf_counter() - t0) * 1e3
+            log(f"bench: {prec} comparison, slice {n + 1}/{nsl} ({len(sl)} triples) done")
+        return math.fsum(x[0] for x in parts), msum, nsl
+
     vs64 = None
     if args.vs_fp64 and args.precision != "fp64":
-        log("bench: one full FP64 step for comparison (not timed as a step)")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        E64, E4_64, E5_64 = energy(ctx, dev, "fp64", stream)
-        torch.cuda.synchronize()
-        ms64 = (time.perf_counter() - t0) * 1e3
-        vs64 = {"fp64_ms_per_step": ms64, "E_fp64": E64, "dE": E - E64,
+        E64, ms64, nsl = sliced("fp64")
+        vs64 = {"fp64_ms_per_step": ms64, "fp64_slices": nsl, "E_fp64": E64, "dE": E - E64,
                 "rel_dE": abs(E - E64) / abs(E64), "speedup_vs_fp64": ms64 / ms,
                 "within_1e-6": abs(E - E64) <= 1e-6 * max(1.0, abs(E64))}
+        if args.vs_fp32 and args.precision != "fp32":
+            E32, ms32, nsl32 = sliced("fp32")
+            vs64["fp32"] = {"ms_per_step": ms32, "slices": nsl32, "E": E32, "dE": E32 - E64,
+                            "rel_dE": abs(E32 - E64) / abs(E64), "speedup_vs_fp64": ms64 / ms32,
+                            "within_1e-6": abs(E32 - E64) <= 1e-6 * max(1.0, abs(E64))}
 
     sample = [tuple(int(x) for x in s.split(",")) for s in args.sample.split(";") if s]
     parity = None
