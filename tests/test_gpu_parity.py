@@ -329,3 +329,31 @@ def test_memory_cap_gives_enomem(ccsdt_mod, monkeypatch):
         c.energy(synth.to_device(p), "fp64")
     assert e.value.status == -2
     c.close()
+
+
+def test_edge_cases(ctx, ccsdt_mod):
+    """Size limits, an empty triple list, triples with i = j = k only, and
+    repeated triples."""
+    import ctypes
+    p = synth.make_problem(4, 20, seed=38)
+    d = synth.to_device(p)
+    lib = ccsdt_mod.load_library()
+    out = (ctypes.c_double * 3)(1.0, 2.0, 3.0)
+    for field, value in (("nvirt", 2049), ("nocc", 1025)):
+        s = ccsdt_mod.make_problem_struct(d)
+        setattr(s, field, value)
+        say(f"limit {field}={value}")
+        assert lib.ccsdt_energy(ctx._h, ctypes.byref(s), 0, None, out) == -1
+        assert list(out) == [1.0, 2.0, 3.0]
+    say("empty triple list")
+    with pytest.raises(ccsdt_mod.CcsdtError) as e:
+        ctx.triple_energies(d, [], "fp64")
+    assert e.value.status == -1
+    say("triples with i = j = k only")
+    assert ctx.triple_energies(d, [(0, 0, 0), (3, 3, 3)], "fp32") == [(0.0, 0.0, 0.0)] * 2
+    say("repeated and zero triples mixed")
+    trips = [(0, 1, 2), (1, 1, 1), (0, 1, 2), (2, 3, 3), (0, 1, 2)]
+    r = ctx.triple_energies(d, trips, "fp64")
+    assert r[0] == r[2] == r[4] and r[1] == (0.0, 0.0, 0.0)
+    ref = oracle.triples_energy(*_args(p), triples=[(0, 1, 2), (2, 3, 3)])
+    assert abs(r[0][0] + r[3][0] - ref[0]) <= 1e-10 * abs(ref[1])
