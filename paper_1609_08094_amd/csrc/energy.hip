@@ -19,8 +19,10 @@
 // of W.  The waves take turns over the SB^3 sub-block orbits (x <= y <= z)
 // inside it.  For each, a wave first issues every load it needs at once --
 // the six permuted sub-blocks W[x][y][z], W[x][z][y], ..., W[z][y][x]
-// (contiguous rows of the blocked layout, W = W_A + W_B summed on the way),
-// the 18 SB x SB sub-blocks of the
+// (each one contiguous SB^3 run of the blocked layout, read with 16-byte
+// loads that cover it in lane order; W = W_A + W_B summed on the way, or,
+// for a triple taken as (p, p, q), W_A added again at the exchanged
+// positions), the 18 SB x SB sub-blocks of the
 // ovov slices (jX|kY), (iX|kY), (iX|jY) over ordered pairs of {x,y,z}, and
 // the t1 / eps_v segments -- parks them in padded LDS, and then evaluates the
 // representatives a <= b <= c of its (b, c) column from LDS alone.
