@@ -122,12 +122,15 @@ __global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict_
     constexpr int RS = SB;
     constexpr int PS = sizeof(WT) == 4 ? 69 : 67;
     constexpr int BLK = SB * PS;          // one W sub-block
-    constexpr int SRS = SB + 1;           // padded S row (doubles)
+    constexpr int SRS = SB + 1;           // padded S row
     constexpr int SBLK = SB * SRS;        // one S sub-block
     constexpr int VPR = 16 / sizeof(WT);  // W elements per 16-byte load
     constexpr int NVL = SB / VPR;         // 16-byte loads per W row
     __shared__ WT lw[EW][6][BLK];
-    __shared__ double ls[EW][18][SBLK];
+    // integral sub-blocks staged in the W precision (FP32 in the mixed paths,
+    // FP64 in the FP64 path): a quarter less LDS per wave in the mixed paths,
+    // four workgroups per compute unit instead of three; Z is formed in FP64
+    __shared__ WT ls[EW][18][SBLK];
     __shared__ double lt[EW][4][3][SB];   // t1_i, t1_j, t1_k, eps_v over sub-blocks x, y, z
     __shared__ double sh[EW];
     const int bid = blockIdx.x;
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict_
     const int nsb = (v + SB - 1) / SB;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     WT(*L)[BLK] = lw[wave];
-    double(*LS)[SBLK] = ls[wave];
+    WT(*LS)[SBLK] = ls[wave];
     double(*LT)[3][SB] = lt[wave];
 
     double e4 = 0.0, e5 = 0.0;
@@ -243,7 +246,7 @@ __global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict_
                     }
             }
 #pragma unroll
-            for (int n = 0; n < 18; ++n) LS[n][r * SRS + cc] = sv[n];
+            for (int n = 0; n < 18; ++n) LS[n][r * SRS + cc] = (WT)sv[n];
             (&LT[0][0][0])[lane] = tv[0];
             if (lane < 32) (&LT[0][0][0])[lane + 64] = tv[1];
         }
