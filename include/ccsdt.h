@@ -58,7 +58,9 @@
  * single precision for the triples-amplitude products); CCSDT_BF16X3 splits
  * each operand x into hi = bf16(x), lo = bf16(x - hi) and accumulates
  * hi*hi + hi*lo + lo*hi on BF16 MFMA in FP32.  In every mode the
- * denominators, the t1 terms and all energy sums are FP64 (Sec. 4).
+ * denominators, the t1 terms and all energy sums are computed in FP64
+ * (Sec. 4); in the FP32 and BF16X3 modes W and the (jb|kc) values entering
+ * the t1 terms are held in FP32.
  *
  * Errors: every function returns CCSDT_OK (0) or a negative status; on error
  * outputs are left untouched, nothing is leaked, no exception crosses the
