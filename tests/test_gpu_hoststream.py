@@ -88,3 +88,30 @@ def test_pageable_host_vvvo_is_rejected(ccsdt_mod):
     assert ccsdt_mod.load_library().ccsdt_energy(ctx._h, ctypes.byref(st), 0, None, out) == -1
     assert "pinned" in ccsdt_mod.load_library().ccsdt_last_error().decode()
     ctx.close()
+
+
+def test_batched_mix_of_host_and_device_vvvo(ccsdt_mod):
+    """A batch whose members hold vvvo on the device or in pinned host memory
+    runs eagerly (no captured graph) and gives each member's single-problem
+    energy bit for bit."""
+    probs = [synth.make_problem(o, v, seed=610 + n) for n, (o, v) in enumerate([(3, 33), (4, 50), (5, 21)])]
+    devs = [synth.to_device(p) for p in probs]
+    mixed = [devs[0], host_problem(devs[1]), devs[2]]
+    ctx = ccsdt_mod.Context()
+    say("batch with one host-resident vvvo")
+    got = ctx.energy_batched(mixed, "fp32")
+    assert ctx.graph_stats() == (0, 0)
+    for d, g in zip(devs, got):
+        assert g == ctx.energy(d, "fp32")
+    ctx.close()
+
+
+def test_host_vvvo_per_triple_energies(ccsdt_mod):
+    p = synth.make_problem(5, 40, seed=615)
+    d = synth.to_device(p)
+    h = host_problem(d)
+    trips = [(0, 1, 2), (1, 1, 4), (2, 3, 3), (0, 0, 0), (1, 2, 4)]
+    ctx = ccsdt_mod.Context()
+    say("per-triple energies with host-resident vvvo")
+    assert ctx.triple_energies(h, trips, "bf16x3") == ctx.triple_energies(d, trips, "bf16x3")
+    ctx.close()
