@@ -173,3 +173,28 @@ def test_autotune_and_plans(ccsdt_mod):
     with pytest.raises(ccsdt_mod.CcsdtError):
         ctx.plan_set("fp64", 130, ccsdt_mod.NTILE_CFG)
     ctx.close()
+
+
+@pytest.mark.parametrize("cfg", [16, 22, 24])
+def test_graph_replays_with_persistent_and_paced_tiles(ccsdt_mod, batch, cfg, monkeypatch):
+    """Captured graphs of the persistent (16), 32x32-block (22) and paced (24,
+    which clears its counters with a kernel before each launch) contraction
+    configurations, replayed with modified inputs, against the eager path."""
+    probs, devs = batch
+    monkeypatch.setenv("CCSDT_TILE", str(cfg))
+    ctx = ccsdt_mod.Context()
+    say(f"graph with tile configuration {cfg}")
+    g0 = ctx.energy_batched(devs, "bf16x3")
+    saved = [d["t1"].clone() for d in devs]
+    for d in devs:
+        d["t1"].mul_(-1.0)
+    torch.cuda.synchronize()
+    g1 = ctx.energy_batched(devs, "bf16x3")
+    e1 = _eager(ctx, devs, "bf16x3", monkeypatch)
+    for d, s in zip(devs, saved):
+        d["t1"].copy_(s)
+    torch.cuda.synchronize()
+    g2 = ctx.energy_batched(devs, "bf16x3")
+    assert g1 == e1 and g2 == g0
+    assert ctx.graph_stats() == (1, 3)
+    ctx.close()
