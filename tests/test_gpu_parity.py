@@ -357,3 +357,17 @@ def test_edge_cases(ctx, ccsdt_mod):
     assert r[0] == r[2] == r[4] and r[1] == (0.0, 0.0, 0.0)
     ref = oracle.triples_energy(*_args(p), triples=[(0, 1, 2), (2, 3, 3)])
     assert abs(r[0][0] + r[3][0] - ref[0]) <= 1e-10 * abs(ref[1])
+
+
+def test_one_shot_entry_point(ctx, ccsdt_mod):
+    """ccsdt_triples_energy (its own context per call) equals the context call
+    bit for bit, and the oracle in FP64."""
+    p = synth.make_problem(5, 37, seed=39)
+    d = synth.to_device(p)
+    ref = oracle.triples_energy(*_args(p))
+    for prec in ("fp64", "fp32", "bf16x3"):
+        say(f"one-shot {prec}")
+        e = ccsdt_mod.triples_energy(d, prec)
+        assert e == ctx.energy(d, prec)[0]
+        assert e == ccsdt_mod.triples_energy(d, prec)
+    assert abs(ccsdt_mod.triples_energy(d, "fp64") - ref[0]) <= 1e-10 * abs(ref[1])
