@@ -400,3 +400,24 @@ def test_calls_on_a_side_stream(ctx, ccsdt_mod):
     dm = dict(nocc=3, nvirt=30, naux=40, eps_o=torch.from_numpy(m["eps_o"]).cuda(),
               eps_v=torch.from_numpy(m["eps_v"]).cuda(), c_ov=torch.from_numpy(m["c_ov"]).cuda())
     assert ctx.rimp2_energy(dm, "fp64", stream=s) == ctx.rimp2_energy(dm, "fp64")
+
+
+def _random_shapes(n=8, seed=2024):
+    rng = np.random.default_rng(seed)
+    return [(int(rng.integers(1, 8)), int(rng.integers(1, 91))) for _ in range(n)]
+
+
+@pytest.mark.parametrize("o,v", _random_shapes())
+def test_random_shapes_all_precisions(ctx, o, v):
+    """Shapes drawn from a fixed seed (o in 1..7, v in 1..90): FP64 against
+    the oracle at 1e-10, FP32 and BF16X3 at the bounds of the odd-shape tests."""
+    p = synth.make_problem(o, v, seed=5000 + 100 * o + v)
+    say(f"random shape o={o} v={v}")
+    ref = oracle.triples_energy(*_args(p))
+    d = synth.to_device(p)
+    E = ctx.energy(d, "fp64")
+    assert abs(E[0] - ref[0]) <= 1e-10 * max(abs(ref[1]), 1e-300)
+    for prec in ("fp32", "bf16x3"):
+        Em = ctx.energy(d, prec)[0]
+        tol = mixed_tol(ref[0]) if prec == "fp32" else max(mixed_tol(ref[0]), 2 * U_TERM["bf16x3"] * abs(ref[1]))
+        assert abs(Em - ref[0]) <= tol, (prec, Em, ref)
