@@ -110,13 +110,39 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+# Element count of every input block as a function of (o, v, naux), from the
+# layouts of include/ccsdt.h.  The library receives bare pointers and cannot
+# check sizes itself; a block shorter than its layout would be read out of
+# bounds, so the binding refuses it.
+_NUMEL = {
+    "eps_o": lambda o, v, q: o,
+    "eps_v": lambda o, v, q: v,
+    "t1": lambda o, v, q: o * v,
+    "t2": lambda o, v, q: o * o * v * v,
+    "vvvo": lambda o, v, q: v * v * v * o,
+    "ovoo": lambda o, v, q: o * v * o * o,
+    "ovov": lambda o, v, q: o * v * o * v,
+    "bvv": lambda o, v, q: v * v * q,
+    "bvo": lambda o, v, q: v * o * q,
+    "c_ov": lambda o, v, q: o * v * q,
+}
+
+
 def _dev_ptrs(prob: dict, fields, host_ok=()) -> list:
     import torch
-    vals = []
+    o, v = int(prob["nocc"]), int(prob["nvirt"])
+    q = int(prob.get("naux", 0))
     for f in fields:
         t = prob[f]
         if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous():
             raise ValueError(f"{f} must be a contiguous float64 tensor")
+        want = _NUMEL[f](o, v, q)
+        if t.numel() != want:
+            raise ValueError(f"{f} has {t.numel()} elements; nocc={o}, nvirt={v}"
+                             + (f", naux={q}" if f in ("bvv", "bvo", "c_ov") else "") + f" need {want}")
+    vals = []
+    for f in fields:
+        t = prob[f]
         if not t.is_cuda and not (f in host_ok and t.is_pinned()):
             raise ValueError(f"{f} must be on the HIP device" + (" or in pinned host memory" if f in host_ok else ""))
         vals.append(ctypes.c_void_p(t.data_ptr()))

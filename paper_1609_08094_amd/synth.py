@@ -43,6 +43,11 @@ MP2_CONFIGS = {
     "M0": dict(o=8, v=60, naux=150),
     "M1": dict(o=119, v=2546, naux=5852),
 }
+# Physically scaled variant: B multiplied by a factor so that |E(T)| of the
+# workload is of physical size (about 0.1-0.3 Eh for seed 0) instead of the
+# 1e2-1e13 Eh the unscaled recipe gives.  Integrals scale as s^2, the MP2
+# doubles as s^2, W as s^4, so E[4] scales as s^8 and E[5] as s^6.
+PHYSICAL_B_SCALE = {"C0": 0.4, "C1": 0.06, "C2": 0.03, "C3": 0.02}
 BATCH_NPROB = 64
 BATCH_O_RANGE = (4, 16)
 BATCH_V_RANGE = (40, 160)
@@ -54,12 +59,15 @@ def _symmetrize_B(B: np.ndarray) -> np.ndarray:
     return up + np.triu(B, 1).transpose(0, 2, 1)
 
 
-def draw_factors(o: int, v: int, seed: int, naux: int | None = None):
-    """Draw (B, eps_o, eps_v, t1) in the fixed order of the recipe."""
+def draw_factors(o: int, v: int, seed: int, naux: int | None = None, b_scale: float = 1.0):
+    """Draw (B, eps_o, eps_v, t1) in the fixed order of the recipe; B is
+    multiplied by ``b_scale`` after the draw (same random stream)."""
     n = o + v
     naux = 3 * n if naux is None else naux
     rng = np.random.default_rng(seed)
     B = _symmetrize_B(rng.normal(0.0, 0.1, size=(naux, n, n)))
+    if b_scale != 1.0:
+        B *= b_scale
     eps_o = rng.uniform(-2.0, -0.3, size=o)
     eps_v = rng.uniform(0.2, 5.0, size=v)
     t1 = rng.normal(0.0, 1e-3, size=(o, v))
@@ -85,13 +93,14 @@ def _mp2_doubles(ovov: np.ndarray, eps_o: np.ndarray, eps_v: np.ndarray) -> np.n
 
 
 def make_problem(o: int, v: int, seed: int = 0, naux: int | None = None,
-                 with_eri: bool = False, with_df: bool = False) -> dict:
+                 with_eri: bool = False, with_df: bool = False, b_scale: float = 1.0) -> dict:
     """Host float64 problem.  ``with_eri`` also returns the full 8-fold
     symmetric ERI tensor ``eri`` (tiny sizes), from which every block is
     sliced so the blocks agree with it bit for bit.  ``with_df`` also returns
     the density-fitting factors with the auxiliary index fastest,
-    bvv[a][b][Q] = B^Q_ab and bvo[c][i][Q] = B^Q_ci, and ``naux``."""
-    B, eps_o, eps_v, t1 = draw_factors(o, v, seed, naux)
+    bvv[a][b][Q] = B^Q_ab and bvo[c][i][Q] = B^Q_ci, and ``naux``.
+    ``b_scale`` multiplies B (see PHYSICAL_B_SCALE)."""
+    B, eps_o, eps_v, t1 = draw_factors(o, v, seed, naux, b_scale)
     O = slice(0, o)
     V = slice(o, o + v)
     out = dict(nocc=o, nvirt=v, eps_o=eps_o, eps_v=eps_v, t1=np.ascontiguousarray(t1))
@@ -157,14 +166,14 @@ def to_device(prob: dict, device="cuda"):
 
 def make_problem_device(o: int, v: int, seed: int = 0, naux: int | None = None,
                         device="cuda", row_chunk: int = 8192, with_vvvo: bool = True,
-                        with_df: bool = False) -> dict:
+                        with_df: bool = False, b_scale: float = 1.0) -> dict:
     """Same recipe and the same random draws as ``make_problem`` (numpy
     PCG64 on the host), with the integral products formed in float64 on the
     GPU, for workloads whose (vv|vo) block does not fit host memory.
     ``with_df`` adds bvv, bvo and naux as in ``make_problem``;
-    ``with_vvvo=False`` skips the (vv|vo) block."""
+    ``with_vvvo=False`` skips the (vv|vo) block; ``b_scale`` multiplies B."""
     import torch
-    B, eps_o, eps_v, t1 = draw_factors(o, v, seed, naux)
+    B, eps_o, eps_v, t1 = draw_factors(o, v, seed, naux, b_scale)
     naux = B.shape[0]
     Bd = torch.from_numpy(B).to(device)
     del B

@@ -68,3 +68,42 @@ def test_plan_and_graph_entry_points_reject_null_context():
     c, r = ctypes.c_int64(), ctypes.c_int64()
     assert lib.ccsdt_graph_stats(None, ctypes.byref(c), ctypes.byref(r)) == -1
     assert "null" in lib.ccsdt_last_error().decode()
+
+
+def _cpu_problem(o=3, v=5):
+    import torch
+    return dict(nocc=o, nvirt=v, eps_o=torch.zeros(o, dtype=torch.float64),
+                eps_v=torch.zeros(v, dtype=torch.float64), t1=torch.zeros(o, v, dtype=torch.float64),
+                t2=torch.zeros(o, o, v, v, dtype=torch.float64), vvvo=torch.zeros(v, v, v, o, dtype=torch.float64),
+                ovoo=torch.zeros(o, v, o, o, dtype=torch.float64), ovov=torch.zeros(o, v, o, v, dtype=torch.float64))
+
+
+@pytest.mark.parametrize("field", ["eps_o", "eps_v", "t1", "t2", "vvvo", "ovoo", "ovov"])
+def test_binding_rejects_a_block_of_the_wrong_size(field):
+    """A block whose element count disagrees with (nocc, nvirt) is refused by
+    the binding before any pointer reaches the library (the library cannot
+    see sizes and would read past the end)."""
+    import torch
+    p = _cpu_problem()
+    p[field] = torch.zeros(p[field].numel() - 1, dtype=torch.float64)
+    with pytest.raises(ValueError, match=field):
+        ccsdt.make_problem_struct(p)
+
+
+def test_binding_rejects_wrong_sizes_for_df_and_mp2():
+    import torch
+    p = _cpu_problem()
+    p.update(naux=4, bvv=torch.zeros(5 * 5 * 4, dtype=torch.float64), bvo=torch.zeros(5 * 3 * 3, dtype=torch.float64))
+    with pytest.raises(ValueError, match="bvo"):
+        ccsdt.make_problem_df_struct(p)
+    m = dict(nocc=3, nvirt=5, naux=4, eps_o=torch.zeros(3, dtype=torch.float64),
+             eps_v=torch.zeros(5, dtype=torch.float64), c_ov=torch.zeros(3 * 5 * 5, dtype=torch.float64))
+    with pytest.raises(ValueError, match="c_ov"):
+        ccsdt.make_mp2_struct(m)
+
+
+def test_binding_size_check_passes_correct_blocks_to_the_device_check():
+    # correctly sized CPU tensors get past the size check and stop at the
+    # device check
+    with pytest.raises(ValueError, match="HIP device"):
+        ccsdt.make_problem_struct(_cpu_problem())
