@@ -304,6 +304,10 @@ def main():
                          "and the library assembles the (vv|vo) operand on the GPU; host: the (vv|vo) block is "
                          "in pinned host memory and streamed by the library (PCIe-inclusive)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--phys", action="store_true",
+                    help="physically scaled variant: B multiplied by the workload's factor in "
+                         "synth.PHYSICAL_B_SCALE so that |E(T)| is of physical size (0.1-1 Eh), where the "
+                         "mixed-precision bar is the literal 1e-6 Eh")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample", default="0,1,2;3,3,17",
                     help="triples for the CPU baseline and the sampled parity, as i,j,k[;i,j,k] "
@@ -359,10 +363,12 @@ def main():
         return bench_mp2(args, budget, torch, ccsdt, synth)
     cfg = synth.CONFIGS[args.config]
     o, v = cfg["o"], cfg["v"]
-    log(f"bench: generating {args.config} o={o} v={v} seed={args.seed}")
+    b_scale = synth.PHYSICAL_B_SCALE[args.config] if args.phys else 1.0
+    log(f"bench: generating {args.config} o={o} v={v} seed={args.seed} b_scale={b_scale}")
     t0 = time.perf_counter()
     df = args.input == "df"
-    dev = synth.make_problem_device(o, v, seed=args.seed, device="cuda", with_vvvo=not df, with_df=df)
+    dev = synth.make_problem_device(o, v, seed=args.seed, device="cuda", with_vvvo=not df, with_df=df,
+                                    b_scale=b_scale)
     energy = ctx_energy_df if df else ctx_energy
     if args.input == "host":
         log("bench: moving vvvo to pinned host memory")
@@ -491,7 +497,8 @@ def main():
         "config": {"workload": f"closed-shell (T) {args.config}: o={o} v={v} naux={3 * (o + v)} "
                                f"seed={args.seed}, {args.precision}"
                                + (", density-fitted (vv|vo) assembled on the GPU" if df else "")
-                               + (", (vv|vo) streamed from pinned host memory" if args.input == "host" else ""),
+                               + (", (vv|vo) streamed from pinned host memory" if args.input == "host" else "")
+                               + (f", physically scaled (B x {b_scale})" if args.phys else ""),
                    "input": args.input,
                    "nocc": o, "nvirt": v, "precision": args.precision, "algorithmic_flops": F},
         "budget": {"seconds": args.budget, "used_s": time.perf_counter() - T_START,

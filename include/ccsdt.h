@@ -39,6 +39,23 @@
  * (kc|jl) = ovoo[k][c][j][l] and (jb|kc) = ovov[j][b][k][c]; no further
  * symmetry of the inputs is assumed.
  *
+ * Entry points (names of the first draft of this interface in brackets):
+ *   ccsdt_triples_energy          one problem, one-shot (own temporary context)
+ *   ccsdt_energy                  one problem on a context, (E, E[4], E[5])
+ *                                 [ccsdt_triples_energy_ctx]
+ *   ccsdt_energy_batched          many problems on a context, one captured graph
+ *                                 [ccsdt_triples_energy_batched; that draft had no
+ *                                 context argument]
+ *   ccsdt_triple_energies         per-triple partials of listed triples
+ *                                 [ccsdt_triple_partials; here with the problem
+ *                                 and precision passed again, not cached]
+ *   ccsdt_debug_w                 W of one triple (problem, precision, stream
+ *                                 added to the draft's signature)
+ *   ccsdt_energy_df, ccsdt_triple_energies_df   density-fitted (vv|vo)
+ *   ccsdt_rimp2_energy, ccsdt_rimp2_pair_energies, ccsdt_rimp2_flops   RI-MP2
+ *   ccsdt_autotune, ccsdt_plan_get, ccsdt_plan_set   tile plans
+ *   ccsdt_graph_stats, ccsdt_profile_*, ccsdt_flops, ccsdt_last_error
+ *
  * Memory and ownership: every input pointer is a DEVICE pointer (for example
  * the data pointer of a contiguous torch.float64 tensor on the HIP device),
  * except that vvvo, the largest block (o*v^3), may instead be page-locked
@@ -58,9 +75,9 @@
  * single precision for the triples-amplitude products); CCSDT_BF16X3 splits
  * each operand x into hi = bf16(x), lo = bf16(x - hi) and accumulates
  * hi*hi + hi*lo + lo*hi on BF16 MFMA in FP32.  In every mode the
- * denominators, the t1 terms and all energy sums are computed in FP64
- * (Sec. 4); in the FP32 and BF16X3 modes W and the (jb|kc) values entering
- * the t1 terms are held in FP32.
+ * denominators, the t1 terms (from the caller's FP64 t1 and (jb|kc)) and
+ * all energy sums are computed in FP64 (Sec. 4); in the FP32 and BF16X3
+ * modes W is held in FP32.
  *
  * Errors: every function returns CCSDT_OK (0) or a negative status; on error
  * outputs are left untouched, nothing is leaked, no exception crosses the

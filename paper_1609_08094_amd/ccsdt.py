@@ -26,7 +26,7 @@ EXPORTS = ("ccsdt_context_create", "ccsdt_context_destroy", "ccsdt_energy", "ccs
            "ccsdt_plan_get", "ccsdt_plan_set", "ccsdt_graph_stats", "ccsdt_energy_df",
            "ccsdt_triple_energies_df", "ccsdt_rimp2_energy", "ccsdt_rimp2_pair_energies", "ccsdt_rimp2_flops")
 DF_FIELDS = ("eps_o", "eps_v", "t1", "t2", "bvv", "bvo", "ovoo", "ovov")
-NTILE_CFG = 25
+NTILE_CFG = 26
 
 
 class CcsdtError(RuntimeError):
@@ -316,3 +316,4 @@ def triples_energy(prob: dict, precision="fp64", stream=None) -> float:
     _check(lib.ccsdt_triples_energy(vals.nocc, vals.nvirt, *[getattr(vals, f) for f in FIELDS],
                                     _prec(precision), _stream(stream), ctypes.byref(e)))
     return e.value
+

@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -306,12 +307,16 @@ int v_bucket(int v) {
     return b;
 }
 
+// The large-tile configuration (25) needs 32x32 MFMA blocks, which FP64
+// lacks; FP64 runs configuration 6 in its place.
+int cfg_for_prec(int prec, int cfg) { return (cfg == 25 && prec == CCSDT_FP64) ? 6 : cfg; }
+
 int tile_cfg_for(const ccsdt_context* ctx, int prec, int v) {
-    if (ctx->forced_cfg >= 0) return ctx->forced_cfg;
+    if (ctx->forced_cfg >= 0) return cfg_for_prec(prec, ctx->forced_cfg);
     int forced = env_int("CCSDT_TILE", -1);
-    if (forced >= 0 && forced < NTILE_CFG) return forced;
+    if (forced >= 0 && forced < NTILE_CFG) return cfg_for_prec(prec, forced);
     auto it = ctx->plans.find({prec, v_bucket(v)});
-    if (it != ctx->plans.end()) return it->second;
+    if (it != ctx->plans.end()) return cfg_for_prec(prec, it->second);
     return v >= 64 ? 6 : 0;
 }
 

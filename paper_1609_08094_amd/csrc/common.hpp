@@ -140,14 +140,14 @@ __host__ __device__ inline int64_t w_index(int a, int b, int c, int nb) {
 // K stages of each other, so that operand rows shared across tiles are still
 // in the XCD's L2 when the other tiles read them.
 struct TileCfg { int bm, bn, lds, nbat; };
-constexpr int NTILE_CFG = 25;
+constexpr int NTILE_CFG = 26;
 constexpr TileCfg TILE_CFGS[NTILE_CFG] = {
     {64, 64, 0, 1},   {128, 64, 0, 1},  {128, 128, 0, 1}, {128, 128, 1, 1}, {128, 256, 1, 1},
     {64, 128, 1, 1},  {128, 128, 2, 1}, {128, 256, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 2},
     {128, 128, 2, 2}, {128, 128, 2, 2}, {128, 128, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 1},
     {128, 128, 2, 2}, {128, 128, 2, 1}, {256, 256, 2, 1}, {256, 128, 2, 1},
     {256, 128, 2, 1}, {128, 256, 2, 1}, {64, 128, 2, 1}, {128, 128, 2, 1}, {128, 256, 2, 1},
-    {128, 128, 2, 1}};
+    {128, 128, 2, 1}, {256, 256, 2, 1}};
 inline int tile_m(int cfg) { return TILE_CFGS[cfg].bm; }
 inline int tile_n(int cfg) { return TILE_CFGS[cfg].bn; }
 inline int tile_nbat(int cfg) { return TILE_CFGS[cfg].nbat; }

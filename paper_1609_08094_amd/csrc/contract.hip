@@ -883,6 +883,237 @@ __global__ __launch_bounds__(NBAT * (128 / WTM) * (128 / WTN) * 64, MINB) void c
     if (active) store_tile<P, MB, NB>(S, pass, beta, m0, n0, vm, vn, lane, acc);
 }
 
+// ---------------------------------------------------------------------------
+// Large-tile kernel (32x32 MFMA blocks: BF16X3 and FP32).  A workgroup of
+// four waves, one per SIMD, owns a 256 x 256 tile of the (row, col) plane of
+// one batch index; each wave accumulates at most 4 x 4 blocks (128 x 128,
+// 256 accumulator registers), so that a K stage of 128-byte rows feeds a
+// wave with half the LDS bytes per MFMA of a 64 x 64 wave tile.  The rows
+// of the tile (256 of A, 256 of B; 64 KB per stage) stream through two LDS
+// stages with global_load_lds, in the chunk order and swizzle of
+// contract_lds_kernel.  Per stage: the MFMAs of each sub-step run from
+// registers while the fragments of the next sub-step are read from LDS; the
+// one barrier of the stage sits before its last sub-step, whose MFMAs then
+// overlap the reads of the next stage's first fragments and the
+// global_load_lds of the stage after that into the buffer just released.
+// One wave per SIMD has no other wave to hide a dependent MFMA behind, so
+// the products are issued product by product across the wave's blocks.
+// Edge tiles split their valid blocks over the four waves along the longer
+// side instead of 2 x 2, so that no wave idles while another does a full
+// tile's work; every wave runs the same loads and barriers.
+constexpr int BIG_T = 256;   // workgroup tile edge
+constexpr int BIG_W = 4;     // blocks per wave and dimension (at most)
+
+template <class P, int RB, int CB>
+__device__ __forceinline__ void big_mma(typename P::Acc (&acc)[BIG_W][BIG_W], const typename P::Frag (&fa)[BIG_W],
+                                        const typename P::Frag (&fb)[BIG_W]) {
+#pragma unroll
+    for (int a = 0; a < RB; ++a)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) P::template mma_t<0>(acc[a][b], fa[a], fb[b]);
+#pragma unroll
+    for (int a = 0; a < RB; ++a)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) P::template mma_t<1>(acc[a][b], fa[a], fb[b]);
+    if constexpr (P::NMMA > 2) {
+#pragma unroll
+        for (int a = 0; a < RB; ++a)
+#pragma unroll
+            for (int b = 0; b < CB; ++b) P::template mma_t<2>(acc[a][b], fa[a], fb[b]);
+    }
+    if constexpr (P::NMMA > 3) {
+#pragma unroll
+        for (int a = 0; a < RB; ++a)
+#pragma unroll
+            for (int b = 0; b < CB; ++b) P::template mma_t<3>(acc[a][b], fa[a], fb[b]);
+    }
+}
+
+template <class P, int RB, int CB>
+__device__ __forceinline__ void big_read(typename P::Frag (&fa)[BIG_W], typename P::Frag (&fb)[BIG_W],
+                                         const char* As, const char* Bs, int g, int sub, int sw) {
+#pragma unroll
+    for (int a = 0; a < RB; ++a) P::load_lds(fa[a], As + a * P::BS * 128, g, sub, sw);
+#pragma unroll
+    for (int b = 0; b < CB; ++b) P::load_lds(fb[b], Bs + b * P::BS * 128, g, sub, sw);
+}
+
+// Spread NR LDS reads (and NV global loads) evenly over NM MFMAs in the
+// schedule of one region.
+template <int NM, int NR, int NV = 0, int I = 0>
+__device__ __forceinline__ void big_interleave() {
+    if constexpr (NR > 0 && I < NR) {
+        constexpr int q = (NM * (I + 1)) / NR - (NM * I) / NR;
+        constexpr int nv = (NV * (I + 1)) / NR - (NV * I) / NR;
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+        if constexpr (nv > 0) __builtin_amdgcn_sched_group_barrier(0x020, nv, 0);   // global loads
+        if constexpr (q > 0) __builtin_amdgcn_sched_group_barrier(0x008, q, 0);   // q MFMAs
+        big_interleave<NM, NR, NV, I + 1>();
+    }
+}
+
+template <class P>
+struct BigFrags {
+    typename P::Frag a[BIG_W], b[BIG_W];
+};
+
+// The K loop of one wave over all stages of the tile (see above).  `gload`
+// requests a stage into a buffer; As/Bs point at this wave's first A / B
+// fragment row in buffer 0.
+template <class P, int RB, int CB, class GL>
+__device__ __forceinline__ void big_loop(typename P::Acc (&acc)[BIG_W][BIG_W], const char* As, const char* Bs,
+                                         int g, int sw, int nsteps, GL&& gload) {
+    constexpr int STAGE = 2 * BIG_T * 128;   // bytes of one LDS stage
+    constexpr int NS = P::NSUB;
+    constexpr int NM = P::NMMA * RB * CB;                    // MFMAs per sub-step
+    constexpr int NR = (RB + CB) * (P::SPLIT ? 2 : 1);       // LDS reads per sub-step
+    static_assert(NS % 2 == 0, "fragment buffers alternate per sub-step");
+    BigFrags<P> f[2];
+    if constexpr (RB > 0 && CB > 0) big_read<P, RB, CB>(f[0].a, f[0].b, As, Bs, g, 0, sw);
+    for (int step = 0; step < nsteps; ++step) {
+        const int off = (step & 1) * STAGE;
+#pragma unroll
+        for (int sub = 0; sub < NS - 1; ++sub) {
+            if constexpr (RB > 0 && CB > 0) {
+                big_read<P, RB, CB>(f[(sub + 1) & 1].a, f[(sub + 1) & 1].b, As + off, Bs + off, g, sub + 1, sw);
+                big_mma<P, RB, CB>(acc, f[sub & 1].a, f[sub & 1].b);
+                big_interleave<NM, NR>();
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // stage step + 1 has landed for every wave and every wave is done
+        // reading this stage's buffer
+        asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        if (step + 2 < nsteps) gload(step + 2, step & 1);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (RB > 0 && CB > 0) {
+            // next stage's first sub-step (stale data after the last stage; unused)
+            big_read<P, RB, CB>(f[0].a, f[0].b, As + (STAGE - off), Bs + (STAGE - off), g, 0, sw);
+            big_mma<P, RB, CB>(acc, f[1].a, f[1].b);
+            big_interleave<NM, NR>();
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+template <class P>
+__global__ __launch_bounds__(256, 1) void contract_big_kernel(const Slot* __restrict__ slots, int nslot, int total) {
+    static_assert(P::BS == 32, "32x32 MFMA blocks");
+    constexpr int RS = 128;
+    constexpr int ROWS = 2 * BIG_T;
+    constexpr int NP = ROWS * (RS / 16) / 256;   // 16-byte loads per thread per stage
+    constexpr int STAGE = ROWS * RS;
+    __shared__ __attribute__((aligned(16))) char lds[2 * STAGE];
+
+    const int bid = xcd_remap(blockIdx.x, total);
+    int pass, beta, tmi, tni;
+    const Slot* S = find_slot(slots, nslot, bid, pass, beta, tmi, tni);
+    const int v = S->v, o = S->o, Kp = S->Kp;
+    const int mt0 = tmi * BIG_T, nt0 = tni * BIG_T;
+    const int mb = min(BIG_T / 32, (v - mt0 + 31) / 32), nb = min(BIG_T / 32, (v - nt0 + 31) / 32);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int r0, rb, c0, cb;
+    if (mb > BIG_W && nb > BIG_W) {
+        r0 = (wave >> 1) * BIG_W;
+        rb = min(BIG_W, mb - r0);
+        c0 = (wave & 1) * BIG_W;
+        cb = min(BIG_W, nb - c0);
+    } else if (mb >= nb) {
+        const int per = (mb + 3) / 4;
+        r0 = wave * per;
+        rb = max(0, min(per, mb - r0));
+        c0 = 0;
+        cb = nb;
+    } else {
+        const int per = (nb + 3) / 4;
+        c0 = wave * per;
+        cb = max(0, min(per, nb - c0));
+        r0 = 0;
+        rb = mb;
+    }
+
+    const int64_t rowbytes = (int64_t)Kp * P::UNITS * sizeof(typename P::E);
+    const int csteps = (int)(rowbytes / RS);
+    const int nsteps = NSEG * csteps;
+    const char* G = static_cast<const char*>(S->gc);
+    const char* T = static_cast<const char*>(S->tc);
+    const int lrow = threadIdx.x >> 3;                // 0..31; load p covers row lrow + 32 p
+    const int pch = (lane & 7) ^ lds_swz_bs<32>(lrow);
+    const int src_col = (P::SPLIT ? (((pch & 3) << 1) | (pch >> 2)) : pch) * 16;
+    int64_t roff[NP];
+    const char* baseA = G;
+    const char* baseB = T;
+    auto set_rows = [&](int sg) {
+        const SegRows g = segment(pass, sg, S->i, S->j, S->k, o, v);
+        baseA = g.aG ? G : T;
+        baseB = g.bG ? G : T;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int r = lrow + 32 * p;
+            if (r < BIG_T) {
+                const int m = min(mt0 + r, v - 1);
+                roff[p] = (g.a0 + beta * g.aB + m * g.aM) * rowbytes + src_col;
+            } else {
+                const int n = min(nt0 + r - BIG_T, v - 1);
+                roff[p] = (g.b0 + beta * g.bB + n * g.bN) * rowbytes + src_col;
+            }
+        }
+    };
+    int ld_sg = 0, ld_c = 0;   // segment and chunk of the stage last requested
+    auto issue = [&](int c, int buf) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const char* src = (p < NP / 2 ? baseA : baseB) + roff[p] + (int64_t)c * RS;
+            char* dst = lds + buf * STAGE + (8 * wave + 32 * p) * RS;
+            __builtin_amdgcn_global_load_lds((const GLOBAL void*)gp(src), (__attribute__((address_space(3))) void*)dst,
+                                             16, 0, 0);
+        }
+    };
+    // stages are requested in order: stage st is chunk st % csteps of segment st / csteps
+    auto gload = [&](int st, int buf) {
+        const int sg = st / csteps;
+        if (sg != ld_sg) {
+            ld_sg = sg;
+            set_rows(sg);
+        }
+        ld_c = st - sg * csteps;
+        issue(ld_c, buf);
+    };
+    static_assert(NP % 2 == 0 && BIG_T % 32 == 0, "A rows are the first half of the loads");
+
+    typename P::Acc acc[BIG_W][BIG_W];
+#pragma unroll
+    for (int a = 0; a < BIG_W; ++a)
+#pragma unroll
+        for (int b = 0; b < BIG_W; ++b) acc[a][b] = typename P::Acc{};
+
+    set_rows(0);
+    issue(0, 0);
+    if (nsteps > 1) {
+        gload(1, 1);
+        asm volatile("s_waitcnt vmcnt(%0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::"n"(NP) : "memory");
+    } else {
+        asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    }
+    const int g = lane >> 5;
+    const int sw = lds_swz_bs<32>(lane & 31);
+    const char* As = lds + (r0 * 32 + (lane & 31)) * RS;
+    const char* Bs = lds + (BIG_T + c0 * 32 + (lane & 31)) * RS;
+#define CCSDT_BIG_CASE(R, C) \
+    case R * 8 + C: big_loop<P, R, C>(acc, As, Bs, g, sw, nsteps, gload); break;
+    switch ((rb > 0 && cb > 0) ? rb * 8 + cb : 0) {
+        CCSDT_BIG_CASE(4, 4) CCSDT_BIG_CASE(4, 3) CCSDT_BIG_CASE(4, 2) CCSDT_BIG_CASE(4, 1)
+        CCSDT_BIG_CASE(3, 4) CCSDT_BIG_CASE(3, 3) CCSDT_BIG_CASE(3, 2) CCSDT_BIG_CASE(3, 1)
+        CCSDT_BIG_CASE(2, 4) CCSDT_BIG_CASE(2, 3) CCSDT_BIG_CASE(2, 2) CCSDT_BIG_CASE(2, 1)
+        CCSDT_BIG_CASE(1, 4) CCSDT_BIG_CASE(1, 3) CCSDT_BIG_CASE(1, 2) CCSDT_BIG_CASE(1, 1)
+        default: big_loop<P, 0, 0>(acc, As, Bs, g, sw, nsteps, gload); break;
+    }
+#undef CCSDT_BIG_CASE
+    if (rb > 0 && cb > 0)
+        store_tile<P, BIG_W, BIG_W>(S, pass, beta, mt0 + r0 * 32, nt0 + c0 * 32, rb, cb, lane, acc);
+}
+
 // Resident workgroups for the persistent kernels: `per_cu` per compute unit,
 // rounded to a multiple of NXCD.
 static int persist_grid(int per_cu) {
@@ -943,6 +1174,12 @@ static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int tot
         case 21: hipLaunchKernelGGL((contract_lds_kernel<P, 32, 64, 128, 3, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 22: hipLaunchKernelGGL((contract_lds_kernel<typename Wide<P>::T, 64, 64, 128, 2, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 23: hipLaunchKernelGGL((contract_lds_kernel<typename Wide<P>::T, 64, 128, 128, 1, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 25:
+            if constexpr (Wide<P>::T::BS == 32)
+                hipLaunchKernelGGL((contract_big_kernel<typename Wide<P>::T>), dim3(total), dim3(256), 0, s, d_slots, nslot, total);
+            else
+                return hipErrorInvalidValue;   // FP64 has no 32x32 MFMA: plans map 25 to 6
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -127,10 +127,10 @@ __global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict_
     constexpr int VPR = 16 / sizeof(WT);  // W elements per 16-byte load
     constexpr int NVL = SB / VPR;         // 16-byte loads per W row
     __shared__ WT lw[EW][6][BLK];
-    // integral sub-blocks staged in the W precision (FP32 in the mixed paths,
-    // FP64 in the FP64 path): a quarter less LDS per wave in the mixed paths,
-    // four workgroups per compute unit instead of three; Z is formed in FP64
-    __shared__ WT ls[EW][18][SBLK];
+    // integral sub-blocks staged in FP64 in every precision, so that Z is
+    // formed from the caller's FP64 integrals (only W carries the precision
+    // of the contraction)
+    __shared__ double ls[EW][18][SBLK];
     __shared__ double lt[EW][4][3][SB];   // t1_i, t1_j, t1_k, eps_v over sub-blocks x, y, z
     __shared__ double sh[EW];
     const int bid = blockIdx.x;
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict_
     const int nsb = (v + SB - 1) / SB;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     WT(*L)[BLK] = lw[wave];
-    WT(*LS)[SBLK] = ls[wave];
+    double(*LS)[SBLK] = ls[wave];
     double(*LT)[3][SB] = lt[wave];
 
     double e4 = 0.0, e5 = 0.0;
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(EW * 64) void energy_kernel(const Slot* __restrict_
                     }
             }
 #pragma unroll
-            for (int n = 0; n < 18; ++n) LS[n][r * SRS + cc] = (WT)sv[n];
+            for (int n = 0; n < 18; ++n) LS[n][r * SRS + cc] = sv[n];
             (&LT[0][0][0])[lane] = tv[0];
             if (lane < 32) (&LT[0][0][0])[lane + 64] = tv[1];
         }

@@ -127,22 +127,38 @@ def test_batched_denominator_errors_name_the_problem(ccsdt_mod, batch):
 
 def test_batch_of_64_uneven_problems(ccsdt_mod):
     """The 64-member batch recipe (o ~ U{4..16}, v ~ U{40..160}), FP32 and
-    BF16X3 against FP64, FP64 against single-problem calls."""
+    BF16X3 against FP64 for every member, FP64 against single-problem calls,
+    and the four cheapest members (generated on the host, same recipe) in all
+    three precisions against the oracle."""
     ctx = ccsdt_mod.Context()
     shapes = synth.batch_shapes(seed=0)
-    devs = []
+    cost = [int(o) ** 3 * int(v) ** 4 for o, v in shapes]
+    small = sorted(range(len(shapes)), key=lambda n: cost[n])[:4]
+    devs, host = [], {}
     for n, (o, v) in enumerate(shapes):
-        devs.append(synth.make_problem_device(int(o), int(v), seed=n, device="cuda"))
+        if n in small:
+            host[n] = synth.make_problem(int(o), int(v), seed=n)
+            devs.append(synth.to_device(host[n]))
+        else:
+            devs.append(synth.make_problem_device(int(o), int(v), seed=n, device="cuda"))
     torch.cuda.synchronize()
     say("batch of 64: fp64")
     e64 = ctx.energy_batched(devs, "fp64")
     for n in (0, 17, 63):
         assert e64[n] == ctx.energy(devs[n], "fp64")
+    em = {}
     for prec in ("fp32", "bf16x3"):
         say(f"batch of 64: {prec}")
-        em = ctx.energy_batched(devs, prec)
-        for a, b in zip(em, e64):
+        em[prec] = ctx.energy_batched(devs, prec)
+        for a, b in zip(em[prec], e64):
             assert abs(a[0] - b[0]) <= 1e-6 * max(1.0, abs(b[0]))
+    for n in small:
+        o, v = shapes[n]
+        say(f"batch member {n} (o={o}, v={v}) against the oracle")
+        ref = oracle.triples_energy(*_args(host[n]))
+        assert abs(e64[n][0] - ref[0]) <= 1e-10 * abs(ref[1])
+        for prec in ("fp32", "bf16x3"):
+            assert abs(em[prec][n][0] - ref[0]) <= 1e-6 * max(1.0, abs(ref[0])), (n, prec, em[prec][n], ref)
     ctx.close()
 
 

@@ -64,14 +64,23 @@ def _oracle_triple(d, t):
                                     host["ovoo"], host["ovov"])
 
 
-@pytest.mark.parametrize("n", [0, 1])
-def test_c3_fp64_triple_against_oracle(c3, n):
+@pytest.mark.parametrize("n", range(len(TRIPS)))
+def test_c3_triple_against_oracle(c3, n):
+    """Each sampled triple in every precision against the oracle: FP64 at
+    1e-10 relative, FP32 and BF16X3 at the mixed bar 1e-6 max(1, |e|) on the
+    triple's energy, and its t1 part e5 within the same absolute budget (e5
+    is a cancelling sum of small terms; its error comes from W alone)."""
     d, res = c3
     t = TRIPS[n]
     ref = _oracle_triple(d, t)
     got = res["fp64"][n]
     assert abs(got[0] - ref[0]) <= 1e-10 * abs(ref[1]), (t, got, ref)
     assert abs(got[2] - ref[2]) <= 1e-10 * abs(ref[1]), (t, got, ref)
+    for prec in ("fp32", "bf16x3"):
+        g = res[prec][n]
+        say(f"  {t} {prec}: de/|e| = {abs(g[0] - ref[0]) / abs(ref[0]):.3e}, de5 = {g[2] - ref[2]:.3e}")
+        assert abs(g[0] - ref[0]) <= 1e-6 * max(1.0, abs(ref[0])), (prec, t, g, ref)
+        assert abs(g[2] - ref[2]) <= 1e-6 * max(1.0, abs(ref[0])), (prec, t, g, ref)
 
 
 def test_c3_mixed_precisions_against_fp64(c3):
