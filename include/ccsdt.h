@@ -51,6 +51,7 @@
  *                                 and precision passed again, not cached]
  *   ccsdt_debug_w                 W of one triple (problem, precision, stream
  *                                 added to the draft's signature)
+ *   ccsdt_energy_noalloc          one problem, no allocation, result on the device
  *   ccsdt_energy_df, ccsdt_triple_energies_df   density-fitted (vv|vo)
  *   ccsdt_rimp2_energy, ccsdt_rimp2_pair_energies, ccsdt_rimp2_flops   RI-MP2
  *   ccsdt_autotune, ccsdt_plan_get, ccsdt_plan_set   tile plans
@@ -145,6 +146,31 @@ int ccsdt_triples_energy(int nocc, int nvirt,
                          const double* t1, const double* t2,
                          const double* vvvo, const double* ovoo, const double* ovov,
                          int precision, void* hip_stream, double* e_out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc): E(T) of one problem
+ * as in ccsdt_energy, with no context, no device or pinned-host allocation
+ * and no host synchronization.  Every workspace buffer (packed operands, W,
+ * partial sums, the triple table) lives in one static device array of
+ * CCSDT_NOALLOC_SCRATCH_BYTES per GPU, which the library holds until the
+ * process ends.  Inputs as for ccsdt_energy, all in device memory (vvvo may
+ * not be host memory here).  out_dev is a DEVICE pointer to 3 doubles that
+ * receives (E(T), E[4], E[5]) when the stream reaches the end of the
+ * enqueued work; the call itself only validates and enqueues.  If an orbital
+ * energy is not finite or max(eps_o) >= min(eps_v), out_dev receives NaN
+ * (the check runs on the device).  Tile configuration: the default of
+ * ccsdt_energy (no tuned plans); both contraction passes run for every
+ * triple, so results agree with ccsdt_energy to rounding, not bit for bit.
+ * A problem whose workspace exceeds the array (packed operands
+ * (o v^2 + o^2 v) roundup(o+v, 32) elements of 8 bytes in FP64 and 4
+ * otherwise, plus the W of at least one triple, 2 ceil(v/16)^3 4096
+ * elements) is rejected with CCSDT_EINVAL and a message giving the size it
+ * needs.  All calls on one GPU share its array: calls that overlap on one
+ * GPU (other streams, other threads) race and give wrong results; calls
+ * ordered on one stream are safe. */
+#define CCSDT_NOALLOC_SCRATCH_BYTES (256u << 20)
+int ccsdt_energy_noalloc(const ccsdt_problem* prob, int precision, void* hip_stream,
+                         double* out_dev);
 
 /* Per-triple energies e_ijk (including the multiplicity m_ijk) of the
  * restricted triples listed in ijk_host[3*n] (each i<=j<=k< nocc; i=j=k

@@ -21,7 +21,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libccsdt.so")
 ARCH = "gfx950"
 
-SOURCES = ["pack.hip", "df.hip", "contract.hip", "energy.hip", "mp2.hip", "api.cpp"]
+SOURCES = ["pack.hip", "df.hip", "contract.hip", "energy.hip", "mp2.hip", "noalloc.hip", "api.cpp"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

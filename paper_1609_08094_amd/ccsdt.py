@@ -24,9 +24,11 @@ EXPORTS = ("ccsdt_context_create", "ccsdt_context_destroy", "ccsdt_energy", "ccs
            "ccsdt_triple_energies", "ccsdt_debug_w", "ccsdt_energy_batched", "ccsdt_profile_enable",
            "ccsdt_profile_get", "ccsdt_profile_reset", "ccsdt_flops", "ccsdt_last_error", "ccsdt_autotune",
            "ccsdt_plan_get", "ccsdt_plan_set", "ccsdt_graph_stats", "ccsdt_energy_df",
-           "ccsdt_triple_energies_df", "ccsdt_rimp2_energy", "ccsdt_rimp2_pair_energies", "ccsdt_rimp2_flops")
+           "ccsdt_triple_energies_df", "ccsdt_rimp2_energy", "ccsdt_rimp2_pair_energies", "ccsdt_rimp2_flops",
+           "ccsdt_energy_noalloc")
+NOALLOC_SCRATCH_BYTES = 256 << 20
 DF_FIELDS = ("eps_o", "eps_v", "t1", "t2", "bvv", "bvo", "ovoo", "ovov")
-NTILE_CFG = 26
+NTILE_CFG = 27
 
 
 class CcsdtError(RuntimeError):
@@ -67,6 +69,7 @@ def load_library(path: str = LIB_PATH):
     lib.ccsdt_context_destroy.argtypes = [vp]
     lib.ccsdt_energy.argtypes = [vp, P, ip, vp, dp]
     lib.ccsdt_triples_energy.argtypes = [ip, ip] + [vp] * 7 + [ip, vp, dp]
+    lib.ccsdt_energy_noalloc.argtypes = [P, ip, vp, vp]
     lib.ccsdt_triple_energies.argtypes = [vp, P, ip, ip, ctypes.POINTER(ctypes.c_int), vp, dp]
     lib.ccsdt_debug_w.argtypes = [vp, P, ip, ip, ip, ip, vp, dp]
     lib.ccsdt_energy_batched.argtypes = [vp, ip, P, ip, vp, dp]
@@ -317,3 +320,19 @@ def triples_energy(prob: dict, precision="fp64", stream=None) -> float:
                                     _prec(precision), _stream(stream), ctypes.byref(e)))
     return e.value
 
+
+def energy_noalloc(prob: dict, precision="fp64", out=None, stream=None):
+    """Enqueue E(T) through ccsdt_energy_noalloc (no device allocation, no
+    synchronization); `out` is a float64 device tensor of 3 elements (made
+    here if None) that holds (E, E4, E5) once the stream has run the work.
+    Returns `out`."""
+    import torch
+    p = make_problem_struct(prob)
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=prob["eps_o"].device)
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64
+            and out.is_contiguous() and out.numel() >= 3):
+        raise ValueError("out must be a contiguous float64 device tensor of at least 3 elements")
+    _check(load_library().ccsdt_energy_noalloc(ctypes.byref(p), _prec(precision), _stream(stream),
+                                               ctypes.c_void_p(out.data_ptr())))
+    return out

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -100,6 +101,13 @@ struct ccsdt_context {
     hipStream_t copy_stream = nullptr;
     hipEvent_t ev_copy[2] = {nullptr, nullptr}, ev_pack[2] = {nullptr, nullptr}, ev_start = nullptr;
     int64_t streamed_bytes = 0;
+    // test hooks, read at creation: CCSDT_FAIL_AT names a kernel class whose
+    // next launch fails with CCSDT_EHIP instead of running; CCSDT_SHUFFLE
+    // (a nonzero seed) shuffles the work list inside each tile plan
+    int fail_at = -1;
+    uint64_t shuffle = 0;
+    GapDesc* host_desc = nullptr;
+    size_t host_desc_bytes = 0;
 
     size_t allocated() const {
         return gc.bytes + tc.bytes + w.bytes + part.bytes + etrip.bytes + slots.bytes + out.bytes + tripbeg.bytes +
@@ -201,8 +209,14 @@ int prof_collect(ccsdt_context* ctx) {
     return CCSDT_OK;
 }
 
+const char* const KERNEL_CLASS_NAMES[K_NCLASS] = {"pack", "contract", "energy", "reduce", "assemble", "mp2_gemm",
+                                                   "mp2_energy"};
+
 #define LAUNCH(cls, expr)                                                                         \
     do {                                                                                          \
+        if (ctx->fail_at == (cls))                                                                \
+            return fail(CCSDT_EHIP, std::string("injected failure (CCSDT_FAIL_AT) before a ") +  \
+                                        KERNEL_CLASS_NAMES[cls] + " launch");                    \
         CHK(prof_begin(ctx, cls, s));                                                             \
         hipError_t e_ = (expr);                                                                   \
         if (e_ != hipSuccess) {                                                                   \
@@ -381,6 +395,11 @@ int plan_pipeline(ccsdt_context* ctx, Plan& P, int prec) {
     }
     // triples of one tile configuration next to each other, so that chunks
     // (which break where the configuration changes) stay few
+    if (ctx->shuffle) {
+        // test hook: any order of the work list gives the same energies
+        std::mt19937_64 rng(ctx->shuffle);
+        std::shuffle(P.trips.begin(), P.trips.end(), rng);
+    }
     std::stable_sort(P.trips.begin(), P.trips.end(), [&](const TripRef& x, const TripRef& y) {
         return P.probs[x.prob].cfg < P.probs[y.prob].cfg;
     });
@@ -763,6 +782,10 @@ int ccsdt_context_create(ccsdt_context** ctx_out) {
     ctx->cap = env_size("CCSDT_MAX_DEVICE_BYTES", 0);
     ctx->w_budget = env_size("CCSDT_W_BYTES", (size_t)4 << 30);
     ctx->stage_budget = env_size("CCSDT_STAGE_BYTES", (size_t)2 << 30);
+    if (const char* f = std::getenv("CCSDT_FAIL_AT"))
+        for (int c = 0; c < K_NCLASS; ++c)
+            if (std::strcmp(f, KERNEL_CLASS_NAMES[c]) == 0) ctx->fail_at = c;
+    ctx->shuffle = env_size("CCSDT_SHUFFLE", 0);
     *ctx_out = ctx;
     return CCSDT_OK;
 }
@@ -786,6 +809,7 @@ int ccsdt_context_destroy(ccsdt_context* ctx) {
     if (ctx->host_out) (void)hipHostFree(ctx->host_out);
     if (ctx->host_slots) (void)hipHostFree(ctx->host_slots);
     if (ctx->host_tb) (void)hipHostFree(ctx->host_tb);
+    if (ctx->host_desc) (void)hipHostFree(ctx->host_desc);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
     return CCSDT_OK;
@@ -816,21 +840,33 @@ int ccsdt_profile_get(ccsdt_context* ctx, int cls, int64_t* launches, double* to
 
 // Eager E(T) of the problems in P (work list already built, trip_begin per
 // problem): pipeline, final reduce, copy of (E, E4, E5) rows to out_host.
+// The denominator check runs on the device with the pipeline (one flag per
+// problem next to its result row), so the call synchronizes once, at the
+// end; a failed check leaves the outputs untouched.
 static int eager_energy(ccsdt_context* ctx, Plan& P, const std::vector<int>& tb, int prec, hipStream_t s,
                         double* out_host) {
     const int nprob = (int)P.probs.size();
-    CHK(run_pipeline(ctx, P, prec, s, nullptr));
     CHK(ensure(ctx, ctx->tripbeg, sizeof(int) * (nprob + 1), "triple ranges"));
     CHK(ensure(ctx, ctx->out, sizeof(double) * 4 * nprob, "result"));
+    CHK(ensure(ctx, ctx->pdesc, sizeof(GapDesc) * nprob, "problem table"));
     CHK(ensure_host((void**)&ctx->host_tb, &ctx->host_tb_bytes, sizeof(int) * (nprob + 1)));
-    CHK(ensure_host((void**)&ctx->host_out, &ctx->host_out_bytes, sizeof(double) * 3 * nprob));
+    CHK(ensure_host((void**)&ctx->host_out, &ctx->host_out_bytes, sizeof(double) * 4 * nprob));
+    CHK(ensure_host((void**)&ctx->host_desc, &ctx->host_desc_bytes, sizeof(GapDesc) * nprob));
+    // the previous call's uploads from these buffers finished before it returned
+    for (int p = 0; p < nprob; ++p)
+        ctx->host_desc[p] = {P.probs[p].p.eps_o, P.probs[p].p.eps_v, P.probs[p].p.nocc, P.probs[p].p.nvirt};
+    double* out = static_cast<double*>(ctx->out.p);
+    HIPCHK(hipMemcpyAsync(ctx->pdesc.p, ctx->host_desc, sizeof(GapDesc) * nprob, hipMemcpyHostToDevice, s));
+    LAUNCH(K_REDUCE, launch_gap_check(static_cast<const GapDesc*>(ctx->pdesc.p), nprob, out + 3 * nprob, s));
+    CHK(run_pipeline(ctx, P, prec, s, nullptr));
     std::memcpy(ctx->host_tb, tb.data(), sizeof(int) * (nprob + 1));
     HIPCHK(hipMemcpyAsync(ctx->tripbeg.p, ctx->host_tb, sizeof(int) * (nprob + 1), hipMemcpyHostToDevice, s));
     LAUNCH(K_REDUCE, launch_final_reduce(static_cast<const int*>(ctx->tripbeg.p), nprob,
-                                         static_cast<const double*>(ctx->etrip.p), static_cast<double*>(ctx->out.p), s));
-    HIPCHK(hipMemcpyAsync(ctx->host_out, ctx->out.p, sizeof(double) * 3 * nprob, hipMemcpyDeviceToHost, s));
+                                         static_cast<const double*>(ctx->etrip.p), out, s));
+    HIPCHK(hipMemcpyAsync(ctx->host_out, out, sizeof(double) * 4 * nprob, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     CHK(prof_collect(ctx));
+    CHK(check_flags(ctx->host_out + 3 * nprob, nprob));
     std::memcpy(out_host, ctx->host_out, sizeof(double) * 3 * nprob);
     return CCSDT_OK;
 }
@@ -849,7 +885,6 @@ static int energy_many(ccsdt_context* ctx, int nprob, const ccsdt_problem* probs
         return energy_graph(ctx, nprob, probs, prec, s, out_host);
 
     prof_start_call(ctx);
-    for (int p = 0; p < nprob; ++p) CHK(check_gap(&probs[p], s, nprob > 1 ? p : -1));
     Plan P;
     std::vector<int> tb;
     whole_problem_plan(P, nprob, probs, tb);
@@ -887,7 +922,6 @@ int ccsdt_energy_df(ccsdt_context* ctx, const ccsdt_problem_df* prob, int precis
     CHK(df_layout(prob, L));
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     prof_start_call(ctx);
-    CHK(check_gap(&L.p, s, -1));
     Plan P;
     std::vector<int> tb;
     whole_problem_plan(P, 1, &L.p, tb);
@@ -913,6 +947,114 @@ int ccsdt_triples_energy(int nocc, int nvirt, const double* eps_o, const double*
     ccsdt_context_destroy(ctx);
     if (rc != CCSDT_OK) return fail(rc, msg);
     *e_out = out[0];
+    return CCSDT_OK;
+}
+
+// ---- allocation-free entry point ----------------------------------------------
+// gfx950 check of a device, once per device.
+static int noalloc_check_arch(int dev) {
+    static std::mutex mu;
+    static signed char state[64] = {};   // 0 unknown, 1 gfx950, -1 other
+    if (dev < 0 || dev >= 64) return fail(CCSDT_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(mu);
+    if (state[dev] == 0) {
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, dev));
+        state[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+    }
+    if (state[dev] < 0) return fail(CCSDT_EUNSUPPORTED, "device is not gfx950");
+    return CCSDT_OK;
+}
+
+static_assert(NOALLOC_SCRATCH_BYTES == CCSDT_NOALLOC_SCRATCH_BYTES, "workspace size of the header and the library");
+
+int ccsdt_energy_noalloc(const ccsdt_problem* prob, int precision, void* hip_stream, double* out_dev) {
+    if (!prob) return fail(CCSDT_EINVAL, "null problem");
+    if (!out_dev) return fail(CCSDT_EINVAL, "null output");
+    CHK(check_prec(precision));
+    CHK(check_problem(prob, -1));
+    if (is_pinned_host_ptr(prob->vvvo))
+        return fail(CCSDT_EINVAL, "vvvo must be device memory for the allocation-free call");
+    if (!is_device_ptr(out_dev)) return fail(CCSDT_EINVAL, "out_dev is not a device pointer");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    CHK(noalloc_check_arch(dev));
+    void* base = nullptr;
+    {
+        const hipError_t e = noalloc_scratch(dev, &base);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CCSDT_EHIP, std::string("workspace symbol lookup failed: ") + hipGetErrorString(e));
+        }
+    }
+    const int prec = precision;
+    const int64_t o = prob->nocc, v = prob->nvirt;
+    const int Kp = round_up((int)(o + v), KPAD);
+    int cfg = env_int("CCSDT_TILE", -1);
+    if (cfg < 0 || cfg >= NTILE_CFG || cfg == 24) cfg = v >= 64 ? 6 : 0;   // 24 needs its own counters
+    cfg = cfg_for_prec(prec, cfg);
+    const int64_t ntrip = o * (o + 1) * (o + 2) / 6 - o;
+    const int nb = (int)((v + WB - 1) / WB);
+    const int64_t norb = (int64_t)nb * (nb + 1) * (nb + 2) / 6;
+    const int tiles_m = (int)((v + tile_m(cfg) - 1) / tile_m(cfg)), tiles_n = (int)((v + tile_n(cfg) - 1) / tile_n(cfg));
+    const int bgroups = (int)((v + tile_nbat(cfg) - 1) / tile_nbat(cfg));
+    const int64_t per_wg = 2 * (int64_t)bgroups * tiles_m * tiles_n;
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t es = elem_bytes(prec);
+    const size_t slots_b = al((size_t)std::max<int64_t>(ntrip, 1) * sizeof(Slot));
+    const size_t tb_b = al(2 * sizeof(int)), desc_b = al(sizeof(GapDesc)), flag_b = al(sizeof(double));
+    const size_t etrip_b = al((size_t)std::max<int64_t>(ntrip, 1) * 3 * sizeof(double));
+    const size_t gc_b = al((size_t)(o * v * v * Kp) * es), tc_b = al((size_t)(o * o * v * Kp) * es);
+    const size_t w_per = al(2 * (size_t)nb * nb * nb * WB * WB * WB * w_bytes(prec));
+    const size_t part_per = al((size_t)norb * 2 * sizeof(double));
+    const size_t fixed = slots_b + tb_b + desc_b + flag_b + etrip_b + gc_b + tc_b;
+    const size_t need_one = fixed + (ntrip > 0 ? w_per + part_per : 0);
+    if (need_one > NOALLOC_SCRATCH_BYTES)
+        return fail(CCSDT_EINVAL, "problem needs " + std::to_string(need_one) + " bytes of workspace; the "
+                                  "allocation-free call has " + std::to_string(NOALLOC_SCRATCH_BYTES));
+    int64_t chunk = ntrip > 0 ? (int64_t)((NOALLOC_SCRATCH_BYTES - fixed) / (w_per + part_per)) : 1;
+    chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, std::max<int64_t>(ntrip, 1)));
+    // keep every flattened grid inside int32
+    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, (INT32_MAX / 2) / std::max<int64_t>(per_wg, norb)));
+
+    char* p = static_cast<char*>(base);
+    Slot* slots = reinterpret_cast<Slot*>(p);           p += slots_b;
+    int* tb = reinterpret_cast<int*>(p);                p += tb_b;
+    GapDesc* desc = reinterpret_cast<GapDesc*>(p);      p += desc_b;
+    double* flag = reinterpret_cast<double*>(p);        p += flag_b;
+    double* etrip = reinterpret_cast<double*>(p);       p += etrip_b;
+    char* gc = p;                                       p += gc_b;
+    char* tc = p;                                       p += tc_b;
+    double* part = reinterpret_cast<double*>(p);        p += (size_t)chunk * part_per;
+    char* w = p;
+
+    NoallocPlan np{};
+    np.slots = slots; np.trip_begin = tb; np.desc = desc;
+    np.ntrip = (int)ntrip; np.chunk = (int)chunk;
+    np.o = (int)o; np.v = (int)v; np.Kp = Kp;
+    np.tiles_m = tiles_m; np.tiles_n = tiles_n; np.nbw = nb; np.bgroups = bgroups;
+    np.per_triple_wg = (int)per_wg; np.norb = (int)norb;
+    np.gc = gc; np.tc = tc; np.w = w; np.w_bytes = w_per;
+    np.eps_o = prob->eps_o; np.eps_v = prob->eps_v; np.t1 = prob->t1; np.ovov = prob->ovov;
+
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    auto launched = [](hipError_t e, const char* what) {
+        if (e == hipSuccess) return (int)CCSDT_OK;
+        (void)hipGetLastError();
+        return fail(CCSDT_EHIP, std::string("launch ") + what + ": " + hipGetErrorString(e));
+    };
+    CHK(launched(launch_noalloc_slots(np, s), "slot table"));
+    CHK(launched(launch_gap_check(desc, 1, flag, s), "denominator check"));
+    CHK(launched(launch_pack(prec, (int)o, (int)v, Kp, prob->vvvo, prob->t2, prob->ovoo, gc, tc, s), "pack"));
+    for (int64_t c0 = 0; c0 < ntrip; c0 += chunk) {
+        const int n = (int)std::min<int64_t>(chunk, ntrip - c0);
+        const Slot* d = slots + c0;
+        CHK(launched(launch_contract(prec, cfg, d, n, (int)(n * per_wg), nullptr, s), "contraction"));
+        CHK(launched(launch_energy(prec, d, n, (int)(n * norb), part, s), "energy"));
+        CHK(launched(launch_slot_reduce(d, n, part, etrip, s), "slot reduce"));
+    }
+    CHK(launched(launch_final_reduce(tb, 1, etrip, out_dev, s), "final reduce"));
+    CHK(launched(launch_noalloc_finish(flag, out_dev, s), "finish"));
     return CCSDT_OK;
 }
 

@@ -108,6 +108,37 @@ struct GapDesc {
 // finite, 2 if the gap is not positive.
 hipError_t launch_gap_check(const GapDesc* d_desc, int nprob, double* flag, hipStream_t s);
 
+// ---- allocation-free entry point (noalloc.hip) -----------------------------
+// Size of the static device workspace (one copy per device).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)256 << 20;
+// Device address of this device's workspace (`dev` must be current); looked
+// up once per device.
+hipError_t noalloc_scratch(int dev, void** out);
+// Everything the device-side slot builder needs: the whole restricted triple
+// list of one problem, cut into chunks of `chunk` triples, each slot with
+// room for both passes (per_triple_wg contraction workgroups), norb energy
+// workgroups and partials, and w_bytes of W.
+struct NoallocPlan {
+    Slot* slots;
+    int* trip_begin;          // [0, ntrip]
+    GapDesc* desc;
+    int ntrip, chunk;
+    int o, v, Kp;
+    int tiles_m, tiles_n, nbw, bgroups;
+    int per_triple_wg, norb;
+    const void* gc;
+    const void* tc;
+    char* w;
+    size_t w_bytes;
+    const double* eps_o;
+    const double* eps_v;
+    const double* t1;
+    const double* ovov;
+};
+hipError_t launch_noalloc_slots(const NoallocPlan& a, hipStream_t s);
+// out[0..2] = NaN when *flag != 0 (failed denominator check).
+hipError_t launch_noalloc_finish(const double* flag, double* out, hipStream_t s);
+
 __host__ __device__ inline int64_t w_index(int a, int b, int c, int nb) {
     const int64_t n8 = 2 * (int64_t)nb;
     return ((((int64_t)(a >> 3) * n8 + (b >> 3)) * n8 + (c >> 3)) << 9) + ((a & 7) << 6) + ((b & 7) << 3) + (c & 7);
@@ -140,14 +171,14 @@ __host__ __device__ inline int64_t w_index(int a, int b, int c, int nb) {
 // K stages of each other, so that operand rows shared across tiles are still
 // in the XCD's L2 when the other tiles read them.
 struct TileCfg { int bm, bn, lds, nbat; };
-constexpr int NTILE_CFG = 26;
+constexpr int NTILE_CFG = 27;
 constexpr TileCfg TILE_CFGS[NTILE_CFG] = {
     {64, 64, 0, 1},   {128, 64, 0, 1},  {128, 128, 0, 1}, {128, 128, 1, 1}, {128, 256, 1, 1},
     {64, 128, 1, 1},  {128, 128, 2, 1}, {128, 256, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 2},
     {128, 128, 2, 2}, {128, 128, 2, 2}, {128, 128, 2, 1}, {128, 128, 2, 2}, {128, 128, 2, 1},
     {128, 128, 2, 2}, {128, 128, 2, 1}, {256, 256, 2, 1}, {256, 128, 2, 1},
     {256, 128, 2, 1}, {128, 256, 2, 1}, {64, 128, 2, 1}, {128, 128, 2, 1}, {128, 256, 2, 1},
-    {128, 128, 2, 1}, {256, 256, 2, 1}};
+    {128, 128, 2, 1}, {256, 256, 2, 1}, {128, 128, 2, 1}};
 inline int tile_m(int cfg) { return TILE_CFGS[cfg].bm; }
 inline int tile_n(int cfg) { return TILE_CFGS[cfg].bn; }
 inline int tile_nbat(int cfg) { return TILE_CFGS[cfg].nbat; }

@@ -236,7 +236,35 @@ __device__ __forceinline__ void pace_step(Pacer& pc) {
     }
 }
 
-template <class P, int WTM, int WTN, int ROWB, bool DIRECT, int WGM = 2, int WGN = 2, bool PACE = false>
+// One LDS stage of a full wave tile (every block valid) with the next
+// stage's NL global_load_lds requests spread over the MFMA stream, one after
+// every MB * NB / NL blocks, instead of issued together before it: a burst
+// of requests fills the vector-memory queue and stalls the wave's MFMA issue
+// until it drains.  The fences keep the compiler from gathering the
+// requests (and their address arithmetic) back into one place.
+template <class P, int MB, int NB, int RS, int NL, class LD>
+__device__ __forceinline__ void lds_stage_spread(typename P::Acc (&acc)[MB][NB], const char* As, const char* Bs, int g,
+                                                 int sw, LD&& issue) {
+    static_assert(P::NSUB == 1 && (MB * NB) % NL == 0, "one sub-step, loads spread evenly");
+    constexpr int PER = MB * NB / NL;
+    typename P::Frag fa[MB], fb[NB];
+#pragma unroll
+    for (int a = 0; a < MB; ++a) P::load_lds(fa[a], As + a * P::BS * RS, g, 0, sw);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) P::load_lds(fb[b], Bs + b * P::BS * RS, g, 0, sw);
+#pragma unroll
+    for (int q = 0; q < MB * NB; ++q) {
+        P::mma(acc[q / NB][q % NB], fa[q / NB], fb[q % NB]);
+        if ((q + 1) % PER == 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            issue((q + 1) / PER - 1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+template <class P, int WTM, int WTN, int ROWB, bool DIRECT, int WGM = 2, int WGN = 2, bool PACE = false,
+          bool SPREAD = false>
 __device__ __forceinline__ void lds_tile(const Slot* __restrict__ slots, int nslot, int bid, char* lds,
                                          Pacer* pc = nullptr) {
     using E = typename P::E;
@@ -349,6 +377,21 @@ __device__ __forceinline__ void lds_tile(const Slot* __restrict__ slots, int nsl
             ++sg_next;
             CCSDT_SET_PTRS(sg_next);
         }
+        if constexpr (SPREAD && DIRECT && P::NSUB == 1) {
+            if (vm == MB && vn == NB) {
+                const char* As = lds + buf * (ROWS * RS) + (wm * WTM + (lane % BS)) * RS;
+                const char* Bs = lds + buf * (ROWS * RS) + (BM + wn * WTN + (lane % BS)) * RS;
+                const int cn = c_next;
+                lds_stage_spread<P, MB, NB, RS, NP>(acc, As, Bs, lane / BS, lds_swz_bs<BS>(lane % BS), [&](int p) {
+                    const char* src = ((lrow + p * RPP) < BM ? baseA : baseB) + roff[p] + (int64_t)cn * ROWB;
+                    char* dst = lds + (buf ^ 1) * (ROWS * RS) + (wave_row0 + p * RPP) * RS;
+                    __builtin_amdgcn_global_load_lds((const GLOBAL void*)gp(src),
+                                                     (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+                });
+                lds_dma_barrier();
+                continue;
+            }
+        }
         if constexpr (DIRECT) {
             CCSDT_GLOAD_DIRECT(c_next, buf ^ 1);
         } else {
@@ -381,6 +424,15 @@ __global__ __launch_bounds__(256, MINB) void contract_lds_kernel(const Slot* __r
                                                                   int total) {
     __shared__ __attribute__((aligned(16))) char lds[lds_tile_bytes<WTM, WTN, ROWB>()];
     lds_tile<P, WTM, WTN, ROWB, DIRECT>(slots, nslot, xcd_remap(blockIdx.x, total), lds);
+}
+
+// Configuration 6 with the next stage's requests spread over the MFMAs of
+// the current one (lds_stage_spread) in full tiles.
+template <class P>
+__global__ __launch_bounds__(256, 2) void contract_lds_spread_kernel(const Slot* __restrict__ slots, int nslot,
+                                                                      int total) {
+    __shared__ __attribute__((aligned(16))) char lds[lds_tile_bytes<64, 64, 128>()];
+    lds_tile<P, 64, 64, 128, true, 2, 2, false, true>(slots, nslot, xcd_remap(blockIdx.x, total), lds);
 }
 
 // Workgroups of WGM x WGN waves (more than 2 x 2): one staged copy of the
@@ -1174,6 +1226,7 @@ static hipError_t contract_impl(int cfg, const Slot* d_slots, int nslot, int tot
         case 21: hipLaunchKernelGGL((contract_lds_kernel<P, 32, 64, 128, 3, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 22: hipLaunchKernelGGL((contract_lds_kernel<typename Wide<P>::T, 64, 64, 128, 2, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 23: hipLaunchKernelGGL((contract_lds_kernel<typename Wide<P>::T, 64, 128, 128, 1, true>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
+        case 26: hipLaunchKernelGGL((contract_lds_spread_kernel<P>), dim3(total), dim3(256), 0, s, d_slots, nslot, total); break;
         case 25:
             if constexpr (Wide<P>::T::BS == 32)
                 hipLaunchKernelGGL((contract_big_kernel<typename Wide<P>::T>), dim3(total), dim3(256), 0, s, d_slots, nslot, total);

@@ -191,7 +191,7 @@ def tile_cases():
     return cases
 
 
-@pytest.mark.parametrize("cfg", list(range(26)))
+@pytest.mark.parametrize("cfg", list(range(27)))
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_every_tile_config(ctx, tile_cases, cfg, prec, monkeypatch):
     monkeypatch.setenv("CCSDT_TILE", str(cfg))
@@ -236,7 +236,7 @@ def test_tile_configs_agree_at_hbm_scale(ctx, hbm_case, monkeypatch):
     o_ref = T.triple_restricted(i, j, k, host["eps_o"], host["eps_v"], host["t1"], host["t2"], vv,
                                 host["ovoo"], host["ovov"])
     assert abs(ref[0][0] - o_ref[0]) <= 1e-10 * abs(o_ref[1])
-    for cfg in range(1, 26):
+    for cfg in range(1, 27):
         monkeypatch.setenv("CCSDT_TILE", str(cfg))
         for prec in ("fp64", "fp32", "bf16x3"):
             say(f"hbm scale cfg {cfg} {prec}")
@@ -442,3 +442,56 @@ def test_random_shapes_all_precisions(ctx, o, v):
         Em = ctx.energy(d, prec)[0]
         say(f"  {prec} dE = {Em - ref[0]:.3e} (E = {ref[0]:.6e})")
         assert abs(Em - ref[0]) <= mixed_tol(ref[0]), (prec, Em, ref)
+
+
+# ------------------------------------------------------------ runtime hooks
+def test_shuffled_work_order_is_bitwise_neutral(ccsdt_mod, monkeypatch):
+    """Any order of the work list (CCSDT_SHUFFLE seeds a shuffle of the
+    triples inside each tile plan, so chunks hold other triples) gives the
+    same energies bit for bit: every triple is computed on its own and the
+    sums run in a fixed order."""
+    probs = [synth.make_problem(6, 70, seed=42), synth.make_problem(5, 41, seed=43)]
+    devs = [synth.to_device(p) for p in probs]
+    c0 = ccsdt_mod.Context()
+    ref = {prec: c0.energy(devs[0], prec) for prec in ("fp64", "fp32", "bf16x3")}
+    ref_b = c0.energy_batched(devs, "fp32")
+    ref_t = c0.triple_energies(devs[0], [(0, 1, 2), (2, 2, 5), (1, 3, 4)], "fp64")
+    c0.close()
+    for seed in ("1", "987654321"):
+        monkeypatch.setenv("CCSDT_SHUFFLE", seed)
+        c1 = ccsdt_mod.Context()
+        say(f"shuffled work list, seed {seed}")
+        for prec, r in ref.items():
+            assert c1.energy(devs[0], prec) == r, prec
+        assert c1.energy_batched(devs, "fp32") == ref_b
+        assert c1.triple_energies(devs[0], [(0, 1, 2), (2, 2, 5), (1, 3, 4)], "fp64") == ref_t
+        c1.close()
+
+
+def test_injected_launch_failures(ccsdt_mod, monkeypatch):
+    """CCSDT_FAIL_AT=<kernel class> makes the next launch of that class
+    return CCSDT_EHIP (nothing is launched on the GPU); the call reports it,
+    leaves its outputs alone, and a context made without the hook works."""
+    import ctypes
+    p = synth.make_problem(4, 30, seed=44)
+    d = synth.to_device(p)
+    for cls in ("pack", "contract", "energy", "reduce"):
+        monkeypatch.setenv("CCSDT_FAIL_AT", cls)
+        c = ccsdt_mod.Context()
+        say(f"injected failure at {cls}")
+        lib = ccsdt_mod.load_library()
+        s = ccsdt_mod.make_problem_struct(d)
+        out = (ctypes.c_double * 3)(1.0, 2.0, 3.0)
+        rc = lib.ccsdt_energy(c._h, ctypes.byref(s), 0, None, out)
+        assert rc == -3 and cls in lib.ccsdt_last_error().decode()
+        assert list(out) == [1.0, 2.0, 3.0]
+        with pytest.raises(ccsdt_mod.CcsdtError) as e:
+            c.energy_batched([d, d], "fp32")
+        assert e.value.status == -3
+        c.close()
+    monkeypatch.delenv("CCSDT_FAIL_AT")
+    torch.cuda.synchronize()
+    c = ccsdt_mod.Context()
+    ref = oracle.triples_energy(*_args(p))
+    assert abs(c.energy(d, "fp64")[0] - ref[0]) <= 1e-10 * abs(ref[1])
+    c.close()
